@@ -1,0 +1,154 @@
+/*
+ * maxsq.h -- C ABI of libmaxsq: maximal all-ones square detection in binary matrices on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Bhandari, "An Efficient Frequency-Based Approach for Maximal Square Detection in
+ * Binary Matrices", Section 1): find the largest contiguous square submatrix made only of
+ * ones.  The per-cell quantity is the side of the largest all-ones square whose
+ * bottom-right corner is that cell, i.e. the dp table of Section 2.1 eq. (1):
+ *     dp[i][j] = A[i][j] ? 1 + min(dp[i-1][j], dp[i][j-1], dp[i-1][j-1]) : 0,
+ * with dp = 0 outside the matrix.  S = max dp; the area Algorithm 1 returns is S * S.
+ * Among the cells with dp == S this library reports the first one in row-major order.
+ * An empty matrix (m == 0 or n == 0) or an all-zero one gives S = 0 (Algorithm 1's early
+ * return) and the corner (-1, -1).
+ *
+ * Data layout
+ *   uint8 input  : row-major, row stride ld_bytes >= n; a cell is 1 iff its byte != 0.
+ *   packed input : row-major uint64 words, row stride ld_words >= ceil(n / 64); column j is
+ *                  bit (j & 63) of word (j >> 6), least significant bit first.  Padding bits
+ *                  (columns >= n) and padding words are ignored; they may hold anything.
+ *   dp map       : int32, row-major, row stride ld_dp >= n (elements).
+ *
+ * Ownership and memory: every buffer argument is caller-owned device memory (a result may
+ * also be pinned host memory from hipHostMalloc).  The library never frees or keeps a caller
+ * pointer after the enqueued work completes.  A context owns only its small device scratch
+ * (sized to the largest matrix it has seen) and its tuning table.
+ *
+ * Streams: every call enqueues its kernels on `stream` (a hipStream_t; NULL = the null
+ * stream) and returns without waiting; results are valid once that stream has reached the
+ * call.  A context's scratch is reused by every call on it, so calls on one context must be
+ * ordered on one stream (or externally serialised); use one context per concurrent stream.
+ *
+ * Errors: arguments are validated before any HIP call, so MS_ERR_INVALID_ARGUMENT is
+ * returned without touching the device.  A failed launch or allocation returns MS_ERR_HIP or
+ * MS_ERR_OUT_OF_MEMORY.  No call aborts or throws across the ABI.
+ *
+ * Context: `ctx` may be NULL in every call below; the library then uses a default context
+ * for the current HIP device, created on first use.
+ */
+#ifndef MAXSQ_H
+#define MAXSQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ms_ctx ms_ctx;
+
+typedef enum {
+    MS_OK = 0,
+    MS_ERR_INVALID_ARGUMENT = 1,
+    MS_ERR_WORKSPACE_TOO_SMALL = 2,
+    MS_ERR_OUT_OF_MEMORY = 3,
+    MS_ERR_HIP = 4,
+    MS_ERR_UNSUPPORTED = 5
+} ms_status;
+
+/* Result: side S and the row-major-first bottom-right corner (row, col) among the cells whose
+ * dp equals S; row = col = -1 when S == 0.  The top-left corner is (row - S + 1, col - S + 1). */
+typedef struct {
+    int64_t side, row, col;
+} ms_square;
+
+/* One matrix of a batch: packed bits in device memory, m x n, row stride ld_words. */
+typedef struct {
+    const uint64_t *bits;
+    int64_t m, n, ld_words;
+} ms_matrix;
+
+/* Tunable launch shapes of one context (see ms_candidate / ms_set_config).
+ *   probe_variant : register tile of the erosion search: 0 = 16 rows per lane, sides up to 16
+ *                   certified per tile; 1 = 32 rows, 16; 2 = 32 rows, 32
+ *   map_cols      : columns per lane of the dp-map pass (4 or 8)
+ *   map_band_rows : minimum row-band height of the dp-map pass (the band is also >= 4 S)
+ * All candidates compute identical results; they differ only in speed. */
+typedef struct {
+    int32_t probe_variant;
+    int32_t map_cols;
+    int32_t map_band_rows;
+} ms_config;
+
+/* Create / destroy a context bound to HIP device `hip_device` (-1 = the current device). */
+ms_status ms_create(ms_ctx **ctx, int hip_device);
+ms_status ms_destroy(ms_ctx *ctx);
+const char *ms_status_string(ms_status s);
+
+/*
+ * Bit-pack a uint8 matrix (the input encoding step of the hot path): d_bits[i][j >> 6] bit
+ * (j & 63) = (d_a[i * ld_bytes + j] != 0).  Writes words 0 .. ceil(n/64) - 1 of every row,
+ * with zero padding bits; words beyond that are left untouched.
+ * Invalid: m or n < 0; d_a or d_bits NULL with m * n > 0; ld_bytes < n;
+ * ld_words < ceil(n/64); m * n overflowing int64.
+ */
+ms_status ms_pack_u8(ms_ctx *ctx, const uint8_t *d_a, int64_t m, int64_t n, int64_t ld_bytes,
+                     uint64_t *d_bits, int64_t ld_words, void *stream);
+
+/*
+ * Largest all-ones square of a packed matrix (Section 1's problem; the quantity that the
+ * paper's Algorithm 1 computes, as the side rather than the area).  Writes one ms_square to
+ * d_out (device or pinned host memory).
+ * Invalid: m or n < 0; d_bits NULL with m * n > 0; d_out NULL; ld_words < ceil(n/64);
+ * m * n >= 2^44.
+ */
+ms_status ms_max_square(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                        int64_t ld_words, ms_square *d_out, void *stream);
+
+/*
+ * Full dp map of Section 2.1 eq. (1) into d_dp (int32, row stride ld_dp elements), plus the
+ * largest square into d_out when d_out is not NULL.  Every cell of the m x n map is written;
+ * elements between n and ld_dp are left untouched.
+ * Invalid: as ms_max_square, plus d_dp NULL with m * n > 0, ld_dp < n, m * ld_dp overflow.
+ */
+ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                        int64_t ld_words, int32_t *d_dp, int64_t ld_dp, ms_square *d_out,
+                        void *stream);
+
+/*
+ * Many matrices in one go.  h_mats is a host copy of the `count` descriptors whose device
+ * copy is d_mats; results go to d_out[0 .. count-1] in the same order.  The work of all
+ * matrices is spread over one persistent launch pulling (matrix, tile) items from a device
+ * queue; the launch sequence is recorded once into a HIP graph and replayed afterwards.
+ * The caller provides the workspace (size from ms_batched_workspace_size with the same
+ * descriptors); the library keeps no pointer to it after the work completes.
+ * Invalid: count < 0; any descriptor invalid as in ms_max_square; NULL pointers with
+ * count > 0.  MS_ERR_WORKSPACE_TOO_SMALL if workspace_bytes is below the required size.
+ */
+ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_t count,
+                                    size_t *bytes);
+ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_matrix *d_mats,
+                                int64_t count, ms_square *d_out, void *d_workspace,
+                                size_t workspace_bytes, void *stream);
+
+/* Autotuning.  ms_num_candidates / ms_candidate enumerate the launch shapes this build can
+ * run; ms_set_config forces one (NULL restores tuned/default choices); ms_get_config reports
+ * the shape that would be used for an m x n matrix.  ms_autotune times every candidate on the
+ * caller's packed matrix (blocking: it synchronises `stream`) and records the fastest for
+ * that matrix's shape bucket; ms_autotune_save / ms_autotune_load persist the table as text.
+ */
+int ms_num_candidates(void);
+ms_status ms_candidate(int index, ms_config *cfg);
+ms_status ms_set_config(ms_ctx *ctx, const ms_config *cfg);
+ms_status ms_get_config(ms_ctx *ctx, int64_t m, int64_t n, ms_config *cfg);
+ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                      int64_t ld_words, int32_t *d_dp_scratch, int64_t ld_dp, void *stream);
+ms_status ms_autotune_save(ms_ctx *ctx, const char *path);
+ms_status ms_autotune_load(ms_ctx *ctx, const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAXSQ_H */

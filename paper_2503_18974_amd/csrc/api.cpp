@@ -1,0 +1,525 @@
+// api.cpp -- the C ABI of libmaxsq: argument validation (before any HIP call), contexts and
+// their device scratch, launch-shape selection and autotuning, and the batched graph cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/maxsq.h"
+#include "launch.hpp"
+
+namespace {
+
+constexpr int64_t POS_LIMIT = int64_t(1) << 44;  // cells addressable by the result key
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool mul_overflows(int64_t a, int64_t b) {
+    return a > 0 && b > 0 && a > INT64_MAX / b;
+}
+
+const ms_config DEFAULT_CONFIG = {1, 4, 64};
+
+struct GraphEntry {
+    const void *mats;
+    int64_t count;
+    const void *out;
+    const void *ws;
+    int variant;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct ms_ctx {
+    int device = 0;
+    int num_cus = 256;
+    // single-matrix scratch: header | saturated-tile list | serial-pass state
+    void *scratch = nullptr;
+    uint64_t sat_cap = 0;
+    int64_t state_words = 0;
+    bool dirty = false;
+    bool has_forced = false;
+    ms_config forced{};
+    std::map<int, ms_config> tuned;
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
+    std::mutex mu;
+};
+
+namespace {
+
+std::mutex g_default_mu;
+std::map<int, ms_ctx *> g_default;
+
+ms_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return MS_OK;
+    if (e == hipErrorOutOfMemory) return MS_ERR_OUT_OF_MEMORY;
+    return MS_ERR_HIP;
+}
+
+ms_status init_ctx(ms_ctx *c, int dev) {
+    if (dev < 0) {
+        if (hipGetDevice(&dev) != hipSuccess) return MS_ERR_HIP;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || dev >= count) return MS_ERR_HIP;
+    c->device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return MS_ERR_HIP;
+    c->num_cus = cus > 0 ? cus : 256;
+    return MS_OK;
+}
+
+ms_status resolve(ms_ctx *ctx, ms_ctx **out) {
+    if (ctx) {
+        *out = ctx;
+        return MS_OK;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MS_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    auto it = g_default.find(dev);
+    if (it != g_default.end()) {
+        *out = it->second;
+        return MS_OK;
+    }
+    ms_ctx *c = new (std::nothrow) ms_ctx();
+    if (!c) return MS_ERR_OUT_OF_MEMORY;
+    ms_status s = init_ctx(c, dev);
+    if (s != MS_OK) {
+        delete c;
+        return s;
+    }
+    g_default[dev] = c;
+    *out = c;
+    return MS_OK;
+}
+
+int bucket_of(int64_t m, int64_t n) {
+    auto lg = [](int64_t v) {
+        int r = 0;
+        while (v > 1 && r < 62) {
+            v >>= 1;
+            ++r;
+        }
+        return r;
+    };
+    return lg(m) * 64 + lg(n);
+}
+
+ms_config config_for(ms_ctx *c, int64_t m, int64_t n) {
+    if (c->has_forced) return c->forced;
+    auto it = c->tuned.find(bucket_of(m, n));
+    return it != c->tuned.end() ? it->second : DEFAULT_CONFIG;
+}
+
+bool config_valid(const ms_config &cfg) {
+    return cfg.probe_variant >= 0 && cfg.probe_variant < mshost::NUM_PROBE_VARIANTS &&
+           (cfg.map_cols == 4 || cfg.map_cols == 8) && cfg.map_band_rows >= 1 &&
+           cfg.map_band_rows <= (1 << 20);
+}
+
+// Make sure the context scratch holds the tile list and serial state for an m x n matrix.
+ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, int variant, hipStream_t stream) {
+    const int64_t nwords = std::max<int64_t>(1, cdiv(n, 64));
+    const uint64_t tiles = (uint64_t)(cdiv(std::max<int64_t>(m, 1), mshost::probe_tile_rows(variant)) *
+                                      cdiv(nwords, mshost::PROBE_TILE_WORDS));
+    if (c->scratch && c->sat_cap >= tiles && c->state_words >= nwords) {
+        if (c->dirty) {
+            if (hipMemsetAsync(c->scratch, 0, sizeof(mshost::ScratchHeader), stream) != hipSuccess)
+                return MS_ERR_HIP;
+            c->dirty = false;
+        }
+        return MS_OK;
+    }
+    const uint64_t cap = std::max<uint64_t>(tiles, c->sat_cap) + 1024;
+    const int64_t words = std::max<int64_t>(nwords, c->state_words);
+    const size_t bytes = sizeof(mshost::ScratchHeader) + cap * sizeof(uint64_t) +
+                         (size_t)words * 64 * 2 * sizeof(int32_t);
+    if (c->scratch) {
+        if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
+        (void)hipFree(c->scratch);
+        c->scratch = nullptr;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return hip_status(e);
+    if (hipMemset(p, 0, sizeof(mshost::ScratchHeader)) != hipSuccess) {
+        (void)hipFree(p);
+        return MS_ERR_HIP;
+    }
+    c->scratch = p;
+    c->sat_cap = cap;
+    c->state_words = words;
+    c->dirty = false;
+    return MS_OK;
+}
+
+mshost::ScratchHeader *hdr_of(ms_ctx *c) { return static_cast<mshost::ScratchHeader *>(c->scratch); }
+uint64_t *sat_of(ms_ctx *c) {
+    return reinterpret_cast<uint64_t *>(static_cast<char *>(c->scratch) +
+                                        sizeof(mshost::ScratchHeader));
+}
+int32_t *state_of(ms_ctx *c) { return reinterpret_cast<int32_t *>(sat_of(c) + c->sat_cap); }
+
+ms_status validate_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t ldw) {
+    if (m < 0 || n < 0 || ldw < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (m == 0 || n == 0) return MS_OK;
+    if (!bits) return MS_ERR_INVALID_ARGUMENT;
+    if (ldw < cdiv(n, 64)) return MS_ERR_INVALID_ARGUMENT;
+    if (mul_overflows(m, n) || m * n >= POS_LIMIT) return MS_ERR_INVALID_ARGUMENT;
+    if (mul_overflows(m, ldw)) return MS_ERR_INVALID_ARGUMENT;
+    return MS_OK;
+}
+
+// Runs the two launches of the largest-square search; result lands in the scratch header.
+ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, int64_t m,
+                         int64_t n, int64_t ldw, ms_square *out, hipStream_t stream) {
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    ms_status s = ensure_scratch(c, m, n, cfg.probe_variant, stream);
+    if (s != MS_OK) return s;
+    mshost::LaunchEnv env{c->num_cus, stream};
+    hipError_t e;
+    if (m == 0 || n == 0) {
+        e = mshost::launch_write_result(env, out, hdr_of(c), out ? 1 : 0);
+    } else {
+        e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
+                                      sat_of(c), c->sat_cap, state_of(c), out);
+    }
+    if (e != hipSuccess) {
+        c->dirty = true;
+        return hip_status(e);
+    }
+    return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ms_status_string(ms_status s) {
+    switch (s) {
+    case MS_OK: return "ok";
+    case MS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case MS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case MS_ERR_OUT_OF_MEMORY: return "out of memory";
+    case MS_ERR_HIP: return "HIP runtime error";
+    case MS_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+ms_status ms_create(ms_ctx **ctx, int hip_device) {
+    if (!ctx || hip_device < -1) return MS_ERR_INVALID_ARGUMENT;
+    *ctx = nullptr;
+    ms_ctx *c = new (std::nothrow) ms_ctx();
+    if (!c) return MS_ERR_OUT_OF_MEMORY;
+    ms_status s = init_ctx(c, hip_device);
+    if (s != MS_OK) {
+        delete c;
+        return s;
+    }
+    *ctx = c;
+    return MS_OK;
+}
+
+ms_status ms_destroy(ms_ctx *ctx) {
+    if (!ctx) return MS_ERR_INVALID_ARGUMENT;
+    {
+        std::lock_guard<std::mutex> lk(g_default_mu);
+        for (auto &kv : g_default)
+            if (kv.second == ctx) return MS_ERR_INVALID_ARGUMENT;  // default contexts live on
+    }
+    if (ctx->scratch || !ctx->graphs.empty()) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    delete ctx;
+    return MS_OK;
+}
+
+ms_status ms_pack_u8(ms_ctx *ctx, const uint8_t *d_a, int64_t m, int64_t n, int64_t ld_bytes,
+                     uint64_t *d_bits, int64_t ld_words, void *stream) {
+    if (m < 0 || n < 0 || ld_bytes < 0 || ld_words < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (m > 0 && n > 0) {
+        if (!d_a || !d_bits || ld_bytes < n || ld_words < cdiv(n, 64))
+            return MS_ERR_INVALID_ARGUMENT;
+        if (mul_overflows(m, n) || mul_overflows(m, ld_bytes) || mul_overflows(m, ld_words))
+            return MS_ERR_INVALID_ARGUMENT;
+    }
+    ms_ctx *c = nullptr;
+    ms_status s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    if (m == 0 || n == 0) return MS_OK;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    mshost::LaunchEnv env{c->num_cus, (hipStream_t)stream};
+    return hip_status(mshost::launch_pack_u8(env, d_a, m, n, ld_bytes, d_bits, ld_words));
+}
+
+ms_status ms_max_square(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                        int64_t ld_words, ms_square *d_out, void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (!d_out) return MS_ERR_INVALID_ARGUMENT;
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    return run_max_square(c, config_for(c, m, n), d_bits, m, n, ld_words, d_out,
+                          (hipStream_t)stream);
+}
+
+ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                        int64_t ld_words, int32_t *d_dp, int64_t ld_dp, ms_square *d_out,
+                        void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (ld_dp < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (m > 0 && n > 0) {
+        if (!d_dp || ld_dp < n || mul_overflows(m, ld_dp)) return MS_ERR_INVALID_ARGUMENT;
+    }
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const ms_config cfg = config_for(c, m, n);
+    hipStream_t st = (hipStream_t)stream;
+    s = run_max_square(c, cfg, d_bits, m, n, ld_words, d_out, st);
+    if (s != MS_OK || m == 0 || n == 0) return s;
+    mshost::LaunchEnv env{c->num_cus, st};
+    hipError_t e = mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m, n,
+                                             ld_words, d_dp, ld_dp, hdr_of(c), state_of(c));
+    return hip_status(e);
+}
+
+ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_t count,
+                                    size_t *bytes) {
+    if (count < 0 || !bytes || (count > 0 && !h_mats)) return MS_ERR_INVALID_ARGUMENT;
+    for (int64_t i = 0; i < count; ++i) {
+        ms_status s = validate_packed(h_mats[i].bits, h_mats[i].m, h_mats[i].n, h_mats[i].ld_words);
+        if (s != MS_OK) return s;
+    }
+    if (count >= (int64_t(1) << 24)) return MS_ERR_INVALID_ARGUMENT;
+    int variant = DEFAULT_CONFIG.probe_variant;
+    if (ctx && ctx->has_forced) variant = ctx->forced.probe_variant;
+    *bytes = mshost::batch_layout(variant, h_mats, count).total;
+    return MS_OK;
+}
+
+ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_matrix *d_mats,
+                                int64_t count, ms_square *d_out, void *d_workspace,
+                                size_t workspace_bytes, void *stream) {
+    if (count < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (count == 0) return MS_OK;
+    if (!h_mats || !d_mats || !d_out || !d_workspace) return MS_ERR_INVALID_ARGUMENT;
+    if (count >= (int64_t(1) << 24)) return MS_ERR_INVALID_ARGUMENT;
+    for (int64_t i = 0; i < count; ++i) {
+        ms_status s = validate_packed(h_mats[i].bits, h_mats[i].m, h_mats[i].n, h_mats[i].ld_words);
+        if (s != MS_OK) return s;
+    }
+    ms_ctx *c = nullptr;
+    ms_status s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const int variant = c->has_forced ? c->forced.probe_variant : DEFAULT_CONFIG.probe_variant;
+    const mshost::BatchLayout L = mshost::batch_layout(variant, h_mats, count);
+    if (workspace_bytes < L.total) return MS_ERR_WORKSPACE_TOO_SMALL;
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    const char *ng = std::getenv("MAXSQ_NO_GRAPH");
+    if (ng && ng[0] == '1') {
+        mshost::LaunchEnv env{c->num_cus, st};
+        return hip_status(mshost::launch_batched(env, variant, d_mats, count, d_out, d_workspace, L));
+    }
+    for (auto &g : c->graphs) {
+        if (g.mats == d_mats && g.count == count && g.out == d_out && g.ws == d_workspace &&
+            g.variant == variant)
+            return hip_status(hipGraphLaunch(g.exec, st));
+    }
+    if (!c->capture_stream) {
+        if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return MS_ERR_HIP;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_status(e);
+    mshost::LaunchEnv env{c->num_cus, c->capture_stream};
+    hipError_t le = mshost::launch_batched(env, variant, d_mats, count, d_out, d_workspace, L);
+    e = hipStreamEndCapture(c->capture_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return MS_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_status(e);
+    if (c->graphs.size() >= 8) {
+        if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back(GraphEntry{d_mats, count, d_out, d_workspace, variant, exec});
+    return hip_status(hipGraphLaunch(exec, st));
+}
+
+int ms_num_candidates(void) { return mshost::NUM_PROBE_VARIANTS * 2 * 3; }
+
+ms_status ms_candidate(int index, ms_config *cfg) {
+    if (!cfg || index < 0 || index >= ms_num_candidates()) return MS_ERR_INVALID_ARGUMENT;
+    static const int bands[3] = {32, 64, 128};
+    cfg->probe_variant = index / 6;
+    cfg->map_cols = (index / 3) % 2 ? 8 : 4;
+    cfg->map_band_rows = bands[index % 3];
+    return MS_OK;
+}
+
+ms_status ms_set_config(ms_ctx *ctx, const ms_config *cfg) {
+    if (cfg && !config_valid(*cfg)) return MS_ERR_INVALID_ARGUMENT;
+    ms_ctx *c = nullptr;
+    ms_status s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->has_forced = cfg != nullptr;
+    if (cfg) c->forced = *cfg;
+    return MS_OK;
+}
+
+ms_status ms_get_config(ms_ctx *ctx, int64_t m, int64_t n, ms_config *cfg) {
+    if (!cfg || m < 0 || n < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (!ctx) {
+        *cfg = DEFAULT_CONFIG;
+        ms_ctx *c = nullptr;
+        if (resolve(nullptr, &c) != MS_OK) return MS_OK;
+        ctx = c;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *cfg = config_for(ctx, m, n);
+    return MS_OK;
+}
+
+ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                      int64_t ld_words, int32_t *d_dp_scratch, int64_t ld_dp, void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (m == 0 || n == 0) return MS_ERR_INVALID_ARGUMENT;
+    if (d_dp_scratch && (ld_dp < n || mul_overflows(m, ld_dp))) return MS_ERR_INVALID_ARGUMENT;
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MS_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MS_ERR_HIP;
+    }
+    auto time_it = [&](auto &&body, float *ms_out) -> ms_status {
+        const int reps = 5;
+        ms_status r = body();  // warm-up
+        if (r != MS_OK) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return MS_ERR_HIP;
+        for (int i = 0; i < reps; ++i) {
+            r = body();
+            if (r != MS_OK) return r;
+        }
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return MS_ERR_HIP;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return MS_ERR_HIP;
+        *ms_out = ms / reps;
+        return MS_OK;
+    };
+    ms_config best = DEFAULT_CONFIG;
+    float best_probe = 1e30f;
+    for (int v = 0; v < mshost::NUM_PROBE_VARIANTS && s == MS_OK; ++v) {
+        ms_config cfg = DEFAULT_CONFIG;
+        cfg.probe_variant = v;
+        float t = 0;
+        s = time_it([&]() { return run_max_square(c, cfg, d_bits, m, n, ld_words, nullptr, st); }, &t);
+        if (s == MS_OK && t < best_probe) {
+            best_probe = t;
+            best.probe_variant = v;
+        }
+    }
+    if (s == MS_OK && d_dp_scratch) {
+        float best_map = 1e30f;
+        for (int i = 0; i < ms_num_candidates() && s == MS_OK; ++i) {
+            ms_config cfg;
+            ms_candidate(i, &cfg);
+            if (cfg.probe_variant != best.probe_variant) continue;
+            float t = 0;
+            s = time_it([&]() {
+                ms_status r = run_max_square(c, cfg, d_bits, m, n, ld_words, nullptr, st);
+                if (r != MS_OK) return r;
+                mshost::LaunchEnv env{c->num_cus, st};
+                return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows,
+                                                            d_bits, m, n, ld_words, d_dp_scratch,
+                                                            ld_dp, hdr_of(c), state_of(c)));
+            }, &t);
+            if (s == MS_OK && t < best_map) {
+                best_map = t;
+                best.map_cols = cfg.map_cols;
+                best.map_band_rows = cfg.map_band_rows;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s == MS_OK) c->tuned[bucket_of(m, n)] = best;
+    return s;
+}
+
+ms_status ms_autotune_save(ms_ctx *ctx, const char *path) {
+    if (!ctx || !path) return MS_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return MS_ERR_INVALID_ARGUMENT;
+    std::fprintf(f, "# maxsq autotune table: bucket probe_variant map_cols map_band_rows\n");
+    for (auto &kv : ctx->tuned)
+        std::fprintf(f, "%d %d %d %d\n", kv.first, kv.second.probe_variant, kv.second.map_cols,
+                     kv.second.map_band_rows);
+    std::fclose(f);
+    return MS_OK;
+}
+
+ms_status ms_autotune_load(ms_ctx *ctx, const char *path) {
+    if (!ctx || !path) return MS_ERR_INVALID_ARGUMENT;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return MS_ERR_INVALID_ARGUMENT;
+    std::map<int, ms_config> table;
+    char line[256];
+    ms_status s = MS_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int b = 0;
+        ms_config cfg{};
+        if (std::sscanf(line, "%d %d %d %d", &b, &cfg.probe_variant, &cfg.map_cols,
+                        &cfg.map_band_rows) != 4 || !config_valid(cfg)) {
+            s = MS_ERR_INVALID_ARGUMENT;
+            break;
+        }
+        table[b] = cfg;
+    }
+    std::fclose(f);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &kv : table) ctx->tuned[kv.first] = kv.second;
+    return MS_OK;
+}
+
+}  // extern "C"

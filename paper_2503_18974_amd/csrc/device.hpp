@@ -1,0 +1,452 @@
+// device.hpp -- device-side building blocks of libmaxsq (gfx950, wave64).
+//
+//  * dprun      : the per-cell side map dp[i][j] (Section 2.1 eq. (1)) evaluated row by row
+//                 over a column window, in the rows-parallel form
+//                     dp = A ? min(H, W, dp[i-1][j-1] + 1) : 0
+//                 where H is the column run of ones ending at (i, j) -- the paper's frequency
+//                 array freq[j] (Section 3, Algorithm 1) -- and W is the row run of ones
+//                 ending at (i, j).  A zero state at the window's top-left edge is exact for
+//                 every cell whose true value is at most the distance to that edge, so bands
+//                 and windows that start at least S rows / columns early are exact.
+//  * tile_search: the greedy validation of Algorithm 1 turned into a bitwise test: does the
+//                 tile contain a k x k all-ones square?  E_k (k x k squares ending at each cell)
+//                 is built by erosion, E_{a+d} = E_a & up_d(E_a) & left_d(E_a) & upleft_d(E_a)
+//                 for d <= a, inside a register tile, with a galloping-then-bisecting search
+//                 over k.  The paper's invariant that a side k + 1 is only considered once k is
+//                 validated is what makes the search monotone (E_{k+1} is a subset of E_k).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msk {
+
+constexpr int WAVE = 64;
+constexpr unsigned long long KEY_POS_MASK = (1ull << 44) - 1;
+
+// Result key: larger side wins, then the smaller row-major position (i * n + j).
+__device__ __forceinline__ unsigned long long make_key(int64_t side, int64_t pos) {
+    return ((unsigned long long)side << 44) | (KEY_POS_MASK - (unsigned long long)pos);
+}
+__device__ __forceinline__ int64_t key_side(unsigned long long k) { return (int64_t)(k >> 44); }
+__device__ __forceinline__ int64_t key_pos(unsigned long long k) {
+    return (int64_t)(KEY_POS_MASK - (k & KEY_POS_MASK));
+}
+
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_relaxed_u32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int64_t o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int32_t o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Word k of a packed row with the padding bits of the last word cleared; 0 beyond the row.
+__device__ __forceinline__ uint64_t row_word(const uint64_t *__restrict__ row, int64_t k,
+                                             int64_t nwords, uint64_t lastmask) {
+    if (k < 0 || k >= nwords) return 0;
+    uint64_t v = row[k];
+    return (k == nwords - 1) ? (v & lastmask) : v;
+}
+
+__device__ __forceinline__ uint64_t last_word_mask(int64_t n) {
+    return (n & 63) ? ((1ull << (n & 63)) - 1) : ~0ull;
+}
+
+// Number of consecutive ones at the top (most significant end) of v.
+__device__ __forceinline__ int32_t leading_ones(uint64_t v) {
+    return (v == ~0ull) ? 64 : (int32_t)__clzll(~v);
+}
+
+// Per-lane running maximum with the first row-major position (for the tracking mode).
+struct Track {
+    int32_t v;
+    int64_t pos;
+};
+
+// Reduce per-lane Track to the wave's (max value, smallest position among lanes at max).
+__device__ __forceinline__ Track wave_track(Track t) {
+    int32_t best = wave_max_i32(t.v);
+    int64_t p = (t.v == best) ? t.pos : INT64_MAX;
+    p = wave_min_i64(p);
+    return Track{best, p};
+}
+
+// ----------------------------------------------------------------------------------------------
+// dprun: dp over rows [rh, rb) x columns [xh, xh + ng * 64 * CPL), zero state above row rh and
+// left of column xh (xh is a multiple of 64).  Lane l of group g owns the CPL consecutive
+// columns xh + g * 64 * CPL + l * CPL + t.  Cells with row >= ra and xa <= col < xb are owned:
+// stored into dp (STORE) and/or folded into the per-lane Track (TRACK).
+//
+// Per row and group: the CPL words of the group are read as wave-uniform values to carry the
+// row run W across words and groups; each lane reads its own word for its bits; the value of
+// dp[i-1][c-1] for a lane's first column comes from the lane to its left (previous row), and
+// for lane 0 from the previous group's last column, saved before that group was overwritten.
+// ----------------------------------------------------------------------------------------------
+template <int NGMAX, int CPL, bool STORE, bool TRACK>
+__device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n, int64_t rh,
+                      int64_t ra, int64_t rb, int64_t xh, int64_t xa, int64_t xb, int ng,
+                      int32_t *__restrict__ dp, int64_t ld_dp, bool vec_ok, Track &tr) {
+    static_assert(CPL == 4 || CPL == 8, "columns per lane");
+    constexpr int GW = 64 * CPL;  // columns per group
+    constexpr int LPW = 64 / CPL; // lanes per word
+    const int lane = __lane_id();
+    const int q = lane / LPW;           // word of the group holding this lane's columns
+    const int b = (lane % LPW) * CPL;   // bit offset of the lane's first column in that word
+    const int64_t nwords = (n + 63) >> 6;
+    const uint64_t lastmask = last_word_mask(n);
+
+    int32_t H[NGMAX][CPL], D[NGMAX][CPL];
+#pragma unroll
+    for (int g = 0; g < NGMAX; ++g)
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            H[g][t] = 0;
+            D[g][t] = 0;
+        }
+
+    for (int64_t i = rh; i < rb; ++i) {
+        const uint64_t *__restrict__ row = bits + i * ldw;
+        const bool own_row = i >= ra;
+        int32_t wcarry = 0;    // row run of ones ending just left of the group
+        int32_t dleft_old = 0; // previous-row dp just left of the group
+#pragma unroll
+        for (int g = 0; g < NGMAX; ++g) {
+            if (g < ng) {
+                const int64_t gw0 = (xh >> 6) + (int64_t)g * CPL;
+                int32_t cin[CPL];
+                int32_t c = wcarry;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    cin[k] = c;
+                    const uint64_t v = row_word(row, gw0 + k, nwords, lastmask);
+                    c = (v == ~0ull) ? c + 64 : leading_ones(v);
+                }
+                wcarry = c;
+                const uint64_t x = row_word(row, gw0 + q, nwords, lastmask);
+                int32_t carry = cin[0];
+#pragma unroll
+                for (int k = 1; k < CPL; ++k) carry = (q == k) ? cin[k] : carry;
+                int32_t wrun = carry;
+                if (b != 0) {
+                    const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
+                    wrun = (lo == b) ? b + carry : lo;
+                }
+                const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
+                int32_t dprev = __shfl_up(D[g][CPL - 1], 1);
+                if (lane == 0) dprev = dleft_old;
+                dleft_old = __shfl(D[g][CPL - 1], WAVE - 1);
+                int32_t w = wrun;
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) {
+                    const int32_t mk = -(int32_t)((nib >> t) & 1u);
+                    const int32_t h = (H[g][t] + 1) & mk;
+                    w = (w + 1) & mk;
+                    const int32_t old = D[g][t];
+                    int32_t d = h < w ? h : w;
+                    d = d < dprev + 1 ? d : dprev + 1;
+                    H[g][t] = h;
+                    D[g][t] = d;
+                    dprev = old;
+                }
+                const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
+                if (own_row) {
+                    if (STORE) {
+                        int32_t *p = dp + i * ld_dp + col;
+                        if (col >= xa && col + CPL <= xb) {
+                            if (vec_ok) {
+#pragma unroll
+                                for (int t = 0; t < CPL; t += 4)
+                                    *reinterpret_cast<int4 *>(p + t) =
+                                        make_int4(D[g][t], D[g][t + 1], D[g][t + 2], D[g][t + 3]);
+                            } else {
+#pragma unroll
+                                for (int t = 0; t < CPL; ++t) p[t] = D[g][t];
+                            }
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < CPL; ++t)
+                                if (col + t >= xa && col + t < xb) p[t] = D[g][t];
+                        }
+                    }
+                    if (TRACK) {
+#pragma unroll
+                        for (int t = 0; t < CPL; ++t) {
+                            const bool own = col + t >= xa && col + t < xb;
+                            if (own && D[g][t] > tr.v) {
+                                tr.v = D[g][t];
+                                tr.pos = i * n + col + t;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Serial evaluation by one wave over the whole matrix, per-column state in global scratch
+// (2 * n int32).  Used only when the square is too large for the windowed passes.  Lane l
+// handles bit l of each word; words are visited left to right, carrying the row run and the
+// previous-row dp of the last column across words in uniform registers.
+// ----------------------------------------------------------------------------------------------
+template <bool STORE>
+__device__ void serial_dp(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                          int32_t *__restrict__ dp, int64_t ld_dp, int32_t *__restrict__ stH,
+                          int32_t *__restrict__ stD, Track &tr) {
+    const int lane = __lane_id();
+    const int64_t nwords = (n + 63) >> 6;
+    const uint64_t lastmask = last_word_mask(n);
+    for (int64_t c = lane; c < nwords * 64; c += WAVE) {
+        stH[c] = 0;
+        stD[c] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    constexpr int UNROLL = 8;
+    for (int64_t i = 0; i < m; ++i) {
+        const uint64_t *__restrict__ row = bits + i * ldw;
+        int32_t wcarry = 0, dleft_old = 0;
+        for (int64_t k0 = 0; k0 < nwords; k0 += UNROLL) {
+            int32_t h0[UNROLL], d0[UNROLL];
+            uint64_t v[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int64_t k = k0 + u;
+                v[u] = row_word(row, k, nwords, lastmask);
+                const int64_t c = k * 64 + lane;
+                h0[u] = (k < nwords) ? stH[c] : 0;
+                d0[u] = (k < nwords) ? stD[c] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int64_t k = k0 + u;
+                if (k >= nwords) break;
+                const int64_t c = k * 64 + lane;
+                const uint64_t x = v[u];
+                const int32_t a = (int32_t)((x >> lane) & 1u);
+                const int32_t lo = (int32_t)__clzll(~(x << (63 - lane)));
+                const int32_t w = a ? ((lo == lane + 1) ? lane + 1 + wcarry : lo) : 0;
+                const int32_t h = a ? h0[u] + 1 : 0;
+                int32_t dprev = __shfl_up(d0[u], 1);
+                if (lane == 0) dprev = dleft_old;
+                dleft_old = __shfl(d0[u], WAVE - 1);
+                int32_t d = h < w ? h : w;
+                d = d < dprev + 1 ? d : dprev + 1;
+                if (!a) d = 0;
+                stH[c] = h;
+                stD[c] = d;
+                if (c < n) {
+                    if (STORE) dp[i * ld_dp + c] = d;
+                    if (d > tr.v) {
+                        tr.v = d;
+                        tr.pos = i * n + c;
+                    }
+                }
+                wcarry = (x == ~0ull) ? wcarry + 64 : leading_ones(x);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Erosion tile: 64 lanes = 16 word columns x 4 row groups; lane (rg, wl) holds RPL consecutive
+// rows of word wl.  Word column 0 is the left halo (its results are not owned); the first
+// KC - 1 rows of row group 0 are the top halo.  With that halo every E_k with k <= KC is exact
+// on the owned cells.
+// ----------------------------------------------------------------------------------------------
+template <int RPL_, int KC_>
+struct TileShape {
+    static constexpr int RPL = RPL_;
+    static constexpr int KC = KC_;
+    static constexpr int NWT = 16;
+    static constexpr int NRG = 4;
+    static constexpr int ROWS = NRG * RPL;
+    static constexpr int HALO = KC - 1;
+    static constexpr int TR = ROWS - HALO;  // owned rows per tile
+    static constexpr int OWN_WORDS = NWT - 1;
+    static_assert(HALO < RPL, "top halo must fit in the first row group");
+    static_assert(KC <= 32 && (KC & (KC - 1)) == 0, "KC power of two <= 32");
+};
+
+template <int RPL, int D>
+__device__ __forceinline__ void erode(const uint64_t (&E)[RPL], uint64_t (&T)[RPL], int rg,
+                                      int wl) {
+    static_assert(D >= 1 && D <= 16 && D <= RPL, "shift");
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        uint64_t up;
+        if (r >= D) {
+            up = E[r - D];
+        } else {
+            const uint64_t v = __shfl_up(E[RPL - D + r], 16);
+            up = rg ? v : 0ull;
+        }
+        T[r] = E[r] & up;
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const uint64_t f = T[r];
+        uint32_t lh = __shfl_up((uint32_t)(f >> 32), 1, 16);
+        lh = wl ? lh : 0u;
+        T[r] = f & ((f << D) | (uint64_t)(lh >> (32 - D)));
+    }
+}
+
+template <int RPL>
+__device__ __forceinline__ void erode_by(const uint64_t (&E)[RPL], uint64_t (&T)[RPL], int d,
+                                         int rg, int wl) {
+    switch (d) {
+    case 1: erode<RPL, 1>(E, T, rg, wl); break;
+    case 2: erode<RPL, 2>(E, T, rg, wl); break;
+    case 4: erode<RPL, 4>(E, T, rg, wl); break;
+    case 8: erode<RPL, 8>(E, T, rg, wl); break;
+    default:
+        if constexpr (RPL >= 16) erode<RPL, 16>(E, T, rg, wl);
+        break;
+    }
+}
+
+template <class TS>
+__device__ __forceinline__ bool any_owned(const uint64_t (&T)[TS::RPL], int rg, bool lane_ok) {
+    uint64_t a = 0, h = 0;
+#pragma unroll
+    for (int r = 0; r < TS::RPL; ++r) {
+        if (r < TS::HALO) h |= T[r];
+        else a |= T[r];
+    }
+    const uint64_t acc = rg ? (a | h) : a;
+    return __ballot(lane_ok && acc != 0) != 0;
+}
+
+// Where the outcome of one tile goes.
+struct TileSink {
+    unsigned long long *key;   // atomicMax target
+    uint32_t *sat_count;       // saturated-tile queue
+    uint64_t *sat_list;
+    uint64_t sat_cap;
+    uint64_t sat_tag;          // high bits stored with the tile id (matrix index when batched)
+};
+
+// Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
+// key with the first owned cell of E_k; a tile whose E_KC is non-empty is "saturated" and queued.
+template <class TS>
+__device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                            int64_t ty, int64_t tx, int64_t tile_id, const TileSink &sink) {
+    constexpr int RPL = TS::RPL;
+    const int lane = __lane_id();
+    const int wl = lane & 15, rg = lane >> 4;
+    const int64_t nwords = (n + 63) >> 6;
+    const int64_t tile_r0 = ty * TS::TR - TS::HALO;
+    const int64_t wlane = tx * TS::OWN_WORDS - 1 + wl;
+    const bool wvalid = wlane >= 0 && wlane < nwords;
+    const uint64_t wmask = (wlane == nwords - 1) ? last_word_mask(n) : ~0ull;
+    uint64_t E[RPL], T[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int64_t row = tile_r0 + rg * RPL + r;
+        E[r] = (wvalid && row >= 0 && row < m) ? (bits[row * ldw + wlane] & wmask) : 0ull;
+    }
+    const bool lane_ok = wl != 0 && wvalid;
+    if (!any_owned<TS>(E, rg, lane_ok)) return;
+
+    int cur = 1;
+    bool saturated = true;
+    while (cur < TS::KC) {
+        erode_by<RPL>(E, T, cur, rg, wl);
+        if (any_owned<TS>(T, rg, lane_ok)) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) E[r] = T[r];
+            cur <<= 1;
+        } else {
+            saturated = false;
+            break;
+        }
+    }
+    if (!saturated) {
+        // the tile's side is in [cur, 2 cur - 1]; skip it if it cannot reach the best so far
+        int64_t best = key_side(load_relaxed(sink.key));
+        if (2 * cur - 1 < best) return;
+        for (int d = cur >> 1; d >= 1; d >>= 1) {
+            erode_by<RPL>(E, T, d, rg, wl);
+            if (any_owned<TS>(T, rg, lane_ok)) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) E[r] = T[r];
+                cur += d;
+            }
+            if (cur + d - 1 < best) return;
+        }
+        if (cur < best) return;
+    }
+    // first owned cell of E_cur in row-major order
+    int64_t pos = INT64_MAX;
+    if (lane_ok) {
+#pragma unroll
+        for (int r = RPL - 1; r >= 0; --r) {
+            const bool owned = rg || r >= TS::HALO;
+            const int64_t row = tile_r0 + rg * RPL + r;
+            if (owned && E[r]) pos = row * n + wlane * 64 + (__ffsll((long long)E[r]) - 1);
+        }
+    }
+    pos = wave_min_i64(pos);
+    if (lane == 0) {
+        atomicMax(sink.key, make_key(cur, pos));
+        if (saturated) {
+            const uint32_t slot = atomicAdd(sink.sat_count, 1u);
+            if (slot < sink.sat_cap) sink.sat_list[slot] = sink.sat_tag | (uint64_t)tile_id;
+        }
+    }
+}
+
+// Exact largest square among the owned cells [ra, rb) x [xa, xb) of a saturated tile (whose
+// side is known to be >= kmin): dprun with a halo U that doubles until the local maximum M
+// satisfies M <= U, which proves every owned value exact.  Returns false if the halo would
+// exceed the widest window (the caller then falls back to the serial pass).
+template <int NGMAX, int CPL>
+__device__ bool exact_region(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                             int64_t ra, int64_t rb, int64_t xa, int64_t xb, int64_t kmin,
+                             Track &out) {
+    constexpr int64_t WIN = (int64_t)NGMAX * 64 * CPL;
+    (void)m;
+    int64_t U = 2 * kmin;
+    for (;;) {
+        const int64_t hc = (U + 63) & ~(int64_t)63;
+        if (hc + 64 > WIN) return false;
+        const int64_t ow = WIN - hc;
+        const int64_t rh = ra - U > 0 ? ra - U : 0;
+        Track tr{0, INT64_MAX};
+        for (int64_t xa_w = xa; xa_w < xb; xa_w += ow) {
+            const int64_t xb_w = xa_w + ow < xb ? xa_w + ow : xb;
+            const int64_t xh_w = xa_w - hc > 0 ? ((xa_w - hc) & ~(int64_t)63) : 0;
+            const int ngw = (int)((xb_w - xh_w + 64 * CPL - 1) / (64 * CPL));
+            dprun<NGMAX, CPL, false, true>(bits, ldw, n, rh, ra, rb, xh_w, xa_w, xb_w, ngw,
+                                           nullptr, 0, false, tr);
+        }
+        Track w = wave_track(tr);
+        if (w.v <= U) {
+            out = w;
+            return true;
+        }
+        U = 2 * (int64_t)w.v;
+    }
+}
+
+} // namespace msk

@@ -1,0 +1,68 @@
+// launch.hpp -- host-side launchers of the libmaxsq kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/maxsq.h"
+
+namespace mshost {
+
+// Device scratch of a context (single-matrix calls).  All counters return to zero at the end
+// of every call, so the scratch needs clearing only once, when it is allocated.
+struct ScratchHeader {
+    unsigned long long key;     // running best (side, position) key
+    uint32_t sat_count;         // saturated tiles queued by the erosion pass
+    uint32_t done;              // waves finished in the exact pass
+    uint32_t serial_flag;       // a saturated tile needs the serial pass
+    uint32_t pad0;
+    ms_square result;           // last result (read by the map pass)
+    uint64_t pad1[2];
+};
+static_assert(sizeof(ScratchHeader) == 64, "header layout");
+
+// Erosion tile variants compiled into the library.
+struct ProbeVariant {
+    int rpl;  // rows per lane
+    int kc;   // largest side certified by the tile's halo
+};
+constexpr int NUM_PROBE_VARIANTS = 3;
+extern const ProbeVariant PROBE_VARIANTS[NUM_PROBE_VARIANTS];
+
+int64_t probe_tile_rows(int variant);           // owned rows per tile
+constexpr int64_t PROBE_TILE_WORDS = 15;        // owned words per tile
+
+struct LaunchEnv {
+    int num_cus;
+    hipStream_t stream;
+};
+
+hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int64_t n,
+                          int64_t ldb, uint64_t *bits, int64_t ldw);
+
+// Largest square of one matrix; result into hdr->result and, if non-null, *out.
+hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
+                             int64_t n, int64_t ldw, ScratchHeader *hdr, uint64_t *sat_list,
+                             uint64_t sat_cap, int32_t *serial_state, ms_square *out);
+
+// dp map of one matrix; reads S from hdr->result (written by launch_max_square).
+hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
+                             const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
+                             int64_t ld_dp, const ScratchHeader *hdr, int32_t *serial_state);
+
+// Write a constant result (empty matrices).
+hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,
+                               int64_t count);
+
+// Batched: workspace layout and launches.
+struct BatchLayout {
+    size_t keys, prefix, counters, sat_list, serial_state, flags, total;
+    uint64_t sat_cap;
+    int64_t max_nwords;
+};
+BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count);
+hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_mats,
+                          int64_t count, ms_square *out, void *ws, const BatchLayout &L);
+
+} // namespace mshost

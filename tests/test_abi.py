@@ -1,0 +1,122 @@
+"""The C ABI library loads, exports every symbol its header declares, and rejects invalid
+arguments before touching the device.  CPU only (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2503_18974_amd as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "maxsq.h")
+
+INVALID = 1
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ms_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = M.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = M.lib()
+    for s in range(6):
+        assert L.ms_status_string(s)
+    assert L.ms_status_string(99) == b"unknown status"
+
+
+OUT = ctypes.create_string_buffer(24)
+P = ctypes.addressof(OUT)  # a non-null pointer; never dereferenced by these calls
+
+
+@pytest.mark.parametrize("args", [
+    (None, None, -1, 5, 1, P, None),          # negative m
+    (None, None, 5, -1, 1, P, None),          # negative n
+    (None, None, 5, 5, 1, P, None),           # null bits with cells
+    (None, P, 5, 130, 2, P, None),            # ld_words < ceil(n/64)
+    (None, P, 5, 5, 1, None, None),           # null result
+    (None, P, 1 << 22, 1 << 22, 1 << 16, P, None),  # m*n beyond the 2^44 key range
+    (None, P, 5, 5, -1, P, None),             # negative ld
+])
+def test_max_square_invalid(args):
+    assert M.lib().ms_max_square(*args) == INVALID
+
+
+@pytest.mark.parametrize("args", [
+    (None, P, 5, 5, 1, None, 5, P, None),     # null map with cells
+    (None, P, 5, 5, 1, P, 4, P, None),        # ld_dp < n
+    (None, P, 5, 5, 1, P, -3, P, None),       # negative ld_dp
+    (None, None, 5, 5, 1, P, 5, P, None),     # null bits
+    (None, P, 1 << 40, 2, 1, P, 1 << 40, P, None),  # m * ld_dp overflows
+])
+def test_square_map_invalid(args):
+    assert M.lib().ms_square_map(*args) == INVALID
+
+
+@pytest.mark.parametrize("args", [
+    (None, None, 5, 5, 5, P, 1, None),        # null input
+    (None, P, 5, 5, 4, P, 1, None),           # ld_bytes < n
+    (None, P, 5, 130, 130, P, 2, None),       # ld_words < ceil(n/64)
+    (None, P, 5, 5, 5, None, 1, None),        # null output
+    (None, P, -2, 5, 5, P, 1, None),          # negative m
+])
+def test_pack_invalid(args):
+    assert M.lib().ms_pack_u8(*args) == INVALID
+
+
+def test_batched_invalid():
+    L = M.lib()
+    size = ctypes.c_size_t()
+    assert L.ms_batched_workspace_size(None, None, -1, ctypes.byref(size)) == INVALID
+    assert L.ms_batched_workspace_size(None, None, 3, ctypes.byref(size)) == INVALID
+    mats = (M._Matrix * 2)(M._Matrix(P, 4, 4, 1), M._Matrix(None, 4, 4, 1))
+    assert L.ms_batched_workspace_size(None, mats, 2, ctypes.byref(size)) == INVALID
+    mats[1] = M._Matrix(P, 4, 200, 3)   # ld_words < ceil(200/64)
+    assert L.ms_batched_workspace_size(None, mats, 2, ctypes.byref(size)) == INVALID
+    assert L.ms_max_square_batched(None, None, P, 1, P, P, 1 << 20, None) == INVALID
+    assert L.ms_max_square_batched(None, mats, P, -1, P, P, 1 << 20, None) == INVALID
+    assert L.ms_max_square_batched(None, mats, None, 2, P, P, 1 << 20, None) == INVALID
+    # count == 0 is a no-op that succeeds without touching the device
+    assert L.ms_max_square_batched(None, None, None, 0, None, None, 0, None) == 0
+
+
+def test_workspace_size_is_host_only():
+    mats = (M._Matrix * 3)(M._Matrix(P, 100, 100, 2), M._Matrix(P, 0, 7, 1),
+                           M._Matrix(P, 4096, 4096, 64))
+    a = M.ms_batched_workspace_size(None, mats, 3)
+    b = M.ms_batched_workspace_size(None, mats, 1)
+    assert a > b > 0
+
+
+def test_candidates_and_config_validation():
+    n = M.ms_num_candidates()
+    assert n >= 6
+    seen = set()
+    for i in range(n):
+        c = M.ms_candidate(i)
+        seen.add(tuple(sorted(c.items())))
+    assert len(seen) == n
+    L = M.lib()
+    bad = M._Config(7, 4, 64)
+    assert L.ms_set_config(None, ctypes.byref(bad)) == INVALID
+    bad = M._Config(0, 5, 64)
+    assert L.ms_set_config(None, ctypes.byref(bad)) == INVALID
+    assert L.ms_candidate(n, ctypes.byref(M._Config())) == INVALID
+
+
+def test_create_rejects_bad_args():
+    L = M.lib()
+    assert L.ms_create(None, 0) == INVALID
+    h = ctypes.c_void_p()
+    assert L.ms_create(ctypes.byref(h), -5) == INVALID
+    assert L.ms_destroy(None) == INVALID

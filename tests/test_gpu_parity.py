@@ -1,0 +1,166 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle, on seeded inputs
+spanning several tiles with ragged tails, edge cases and every launch-shape candidate."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+import paper_2503_18974_amd as M
+from gpu_util import announce, set_padding_bits, to_dev_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(a_u8, dev, ctx=None, ld_extra=0, pad_ones=False, dp_extra=0):
+    import torch
+    m, n = a_u8.shape
+    bits = oracle.pack(a_u8)
+    if pad_ones:
+        bits = set_padding_bits(bits, n)
+    d = to_dev_bits(bits, dev, ld_words=W.words_per_row(n) + ld_extra,
+                    pad_fill=0xFFFFFFFFFFFFFFFF if pad_ones else 0)
+    sq = M.max_square(d, n, ctx=ctx)
+    dp = torch.full((m, n + dp_extra), -7, dtype=torch.int32, device=dev)
+    dpv = dp[:, :n] if dp_extra else dp
+    _, sq2 = M.square_map(d, n, ctx=ctx, dp=dpv)
+    ref_dp, ref = oracle.square_map(a_u8)
+    got = dp.cpu().numpy()
+    return sq, sq2, got, ref, ref_dp
+
+
+def assert_same(a_u8, dev, **kw):
+    sq, sq2, got, ref, ref_dp = run_both(a_u8, dev, **kw)
+    n = a_u8.shape[1]
+    assert (sq.side, sq.row, sq.col) == ref, (sq, ref)
+    assert (sq2.side, sq2.row, sq2.col) == ref, (sq2, ref)
+    np.testing.assert_array_equal(got[:, :n], ref_dp)
+    if got.shape[1] > n:
+        assert (got[:, n:] == -7).all(), "map wrote beyond n"
+
+
+SHAPES = [(1, 1), (1, 200), (200, 1), (2, 3), (63, 64), (64, 65), (65, 127), (127, 128),
+          (129, 129), (300, 1000), (1000, 63), (257, 4097), (1500, 1100)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+@pytest.mark.parametrize("p", [0.5, 0.9])
+def test_random_shapes(dev, m, n, p):
+    announce("random", m, n, p)
+    a = W.gen_bernoulli(m, n, p, 1000 * m + n)
+    assert_same(a, dev)
+
+
+@pytest.mark.parametrize("p", [0.0, 0.05, 0.3, 0.7, 0.95, 0.99, 1.0])
+def test_densities(dev, p):
+    announce("density", p)
+    a = W.gen_bernoulli(700, 900, p, 7)
+    assert_same(a, dev)
+
+
+def test_padding_ones_and_strides(dev):
+    announce("padding")
+    for (m, n) in [(50, 70), (33, 130), (200, 191)]:
+        a = W.gen_bernoulli(m, n, 0.8, m + n)
+        assert_same(a, dev, ld_extra=3, pad_ones=True, dp_extra=5)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (64, 64), (300, 17), (17, 300), (2100, 2100)])
+def test_all_ones(dev, m, n):
+    announce("all-ones", m, n)
+    a = np.ones((m, n), np.uint8)
+    assert_same(a, dev)
+
+
+def test_all_zeros_and_empty(dev):
+    import torch
+    announce("zeros/empty")
+    assert_same(np.zeros((130, 70), np.uint8), dev)
+    for m, n in [(0, 0), (0, 5), (5, 0)]:
+        d = torch.zeros((max(m, 1), max(W.words_per_row(n), 1)), dtype=torch.int64, device=dev)[:m]
+        sq = M.max_square(d, n)
+        assert (sq.side, sq.row, sq.col) == (0, -1, -1)
+
+
+@pytest.mark.parametrize("phase", [0, 1])
+def test_checkerboard(dev, phase):
+    announce("checkerboard", phase)
+    i, j = np.indices((333, 517))
+    assert_same((((i + j + phase) % 2) == 0).astype(np.uint8), dev)
+
+
+@pytest.mark.parametrize("side", [1, 15, 16, 17, 31, 32, 33, 64, 65, 200, 700])
+def test_planted_blocks(dev, side):
+    """Squares around the erosion tile's certified bound and the window sizes."""
+    announce("planted", side)
+    rng = np.random.default_rng(side)
+    m, n = 1200, 1500
+    a = (rng.random((m, n)) < 0.6).astype(np.uint8)
+    r0, c0 = int(rng.integers(0, m - side)), int(rng.integers(0, n - side))
+    a[r0:r0 + side, c0:c0 + side] = 1
+    assert_same(a, dev)
+
+
+def test_blob(dev):
+    announce("blob")
+    a = W.gen_blob(1024, 1536, 8.0, 60.0, 3)
+    assert_same(a, dev)
+
+
+def test_every_candidate_identical(dev):
+    """Every launch shape gives the same bits (a race or a missed barrier would differ)."""
+    import torch
+    rng = np.random.default_rng(11)
+    a = (rng.random((900, 1300)) < 0.85).astype(np.uint8)
+    a[100:160, 200:260] = 1
+    ref_dp, ref = oracle.square_map(a)
+    d = to_dev_bits(oracle.pack(a), dev)
+    ctx = M.Context()
+    try:
+        for i in range(M.ms_num_candidates()):
+            cfg = M.ms_candidate(i)
+            announce("candidate", cfg)
+            M.ms_set_config(ctx.handle, cfg)
+            sq = M.max_square(d, 1300, ctx=ctx)
+            dp, sq2 = M.square_map(d, 1300, ctx=ctx)
+            assert (sq.side, sq.row, sq.col) == ref
+            assert (sq2.side, sq2.row, sq2.col) == ref
+            assert torch.equal(dp.cpu(), torch.from_numpy(ref_dp))
+    finally:
+        ctx.close()
+
+
+def test_pack_parity(dev):
+    import torch
+    rng = np.random.default_rng(5)
+    for (m, n) in [(1, 1), (3, 15), (7, 16), (5, 17), (9, 64), (11, 100), (40, 1000), (64, 4099)]:
+        announce("pack", m, n)
+        a = rng.integers(0, 4, size=(m, n)).astype(np.uint8)   # non-zero bytes other than 1
+        ref = oracle.pack(a)
+        ta = torch.from_numpy(a).to(dev)
+        got = M.pack_u8(ta).cpu().numpy().view(np.uint64)
+        np.testing.assert_array_equal(got[:, : ref.shape[1]], ref)
+        # unaligned row stride: a view into a wider buffer, offset by 3 bytes
+        wide = torch.zeros((m, n + 13), dtype=torch.uint8, device=dev)
+        wide[:, 3:3 + n] = ta
+        got2 = M.pack_u8(wide[:, 3:3 + n]).cpu().numpy().view(np.uint64)
+        np.testing.assert_array_equal(got2[:, : ref.shape[1]], ref)
+
+
+def test_c1(dev):
+    """1000 x 1000 Bernoulli(0.7) from seed 0: side, corner and the full int32 map."""
+    announce("c1")
+    a = W.c1()
+    assert_same(a, dev)
+
+
+def test_repeated_calls_reuse_scratch(dev):
+    """The scratch clears itself: alternating inputs give each input's own answer."""
+    announce("repeat")
+    a1 = W.gen_bernoulli(500, 700, 0.9, 1)
+    a2 = np.zeros((800, 300), np.uint8)
+    a3 = W.gen_bernoulli(64, 64, 0.99, 2)
+    ds = [(to_dev_bits(oracle.pack(a), dev), a.shape[1], oracle.max_square(a)) for a in (a1, a2, a3)]
+    for _ in range(3):
+        for d, n, ref in ds:
+            sq = M.max_square(d, n)
+            assert (sq.side, sq.row, sq.col) == ref
