@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the maximal-square hot path on one MI355X.
+
+Workload (the paper's experimental shape, Section 4): 45 square Bernoulli matrices, n in
+{1000, 2000, 3000, 4000, 5000} x p in {0.1, ..., 0.9}, seed 10 n + 10 p, uint8 row-major,
+resident in HBM before timing.  One step = for every matrix, the plain one-launch-per-matrix
+path: bit-pack (ms_pack_u8), largest square (ms_max_square: erosion search and exact pass),
+and the int32 dp map (ms_square_map_from_max).  value = total cells per second over the
+timed steps.
+
+Also reported: the dp-map kernel's achieved algorithmic bandwidth (HIP events around every
+map launch inside the timed steps) against the 8 TB/s HBM peak, the batched entry point over
+the same 45 packed matrices next to the per-matrix loop, and the CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcells/s plain vs batched, % of HBM roofline; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+MAP_BYTES_PER_CELL = 4.0 + 0.125   # int32 map written once + packed input read once
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(mats, budget_s):
+    """The oracle as it stands (plain C dp, full table) on a bounded sample of the workload."""
+    import oracle
+    done_cells, t_total, names = 0, 0.0, []
+    for (n, d, p, seed), a in mats:
+        t0 = time.perf_counter()
+        oracle.square_map(a)
+        t_total += time.perf_counter() - t0
+        done_cells += a.size
+        names.append("%dx%d p=%.1f" % (n, n, p))
+        if t_total > budget_s:
+            break
+    return {"value": done_cells / t_total / 1e9, "unit": "Gcells/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of the 45 grid matrices (%s ...), %.0f Mcells, one full-table dp pass "
+                      "each, %.1f s" % (len(names), ", ".join(names[:3]), done_cells / 1e6, t_total)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes
+    import numpy as np
+    import torch
+    import paper_2503_18974_amd as M
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = M.lib()
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_configs.json")))["c2"]
+
+    log("generating the 45-matrix grid")
+    mats = [((n, d, p, seed), W.gen_bernoulli(n, n, p, seed)) for n, d, p, seed in W.paper_grid()]
+    cells = sum(a.size for _, a in mats)
+    A, B, DP = [], [], []
+    for (n, d, p, seed), a in mats:
+        A.append(torch.from_numpy(a).to(dev))
+        B.append(torch.empty((n, W.words_per_row(n)), dtype=torch.int64, device=dev))
+        DP.append(torch.empty((n, n), dtype=torch.int32, device=dev))
+    RES = torch.zeros((len(mats), 3), dtype=torch.int64, device=dev)
+    ctx = M.Context()
+    h = ctx.handle
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    calls = []
+    for i, ((n, d, p, seed), a) in enumerate(mats):
+        calls.append((n, A[i].data_ptr(), B[i].data_ptr(), B[i].stride(0), DP[i].data_ptr(),
+                      RES[i].data_ptr()))
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in mats] for _ in range(args.steps)]
+
+    def step(evs):
+        for i, (n, pa, pb, ldw, pdp, pres) in enumerate(calls):
+            if L.ms_pack_u8(h, pa, n, n, n, pb, ldw, sp):
+                raise RuntimeError("ms_pack_u8 failed")
+            if L.ms_max_square(h, pb, n, n, ldw, pres, sp):
+                raise RuntimeError("ms_max_square failed")
+            if evs:
+                evs[i][0].record(stream)
+            if L.ms_square_map_from_max(h, pb, n, n, ldw, pres, pdp, n, sp):
+                raise RuntimeError("ms_square_map_from_max failed")
+            if evs:
+                evs[i][1].record(stream)
+
+    log("warmup", args.warmup)
+    for _ in range(max(args.warmup, 1)):
+        step(None)
+    torch.cuda.synchronize()
+    res = RES.cpu().numpy()
+    for i, ((n, d, p, seed), a) in enumerate(mats):
+        g = golden["%d_%d" % (n, d)]
+        if tuple(res[i]) != (g["side"], g["row"], g["col"]):
+            raise SystemExit("result mismatch on %dx%d p=%.1f: %s vs oracle %s"
+                             % (n, n, p, tuple(res[i]), (g["side"], g["row"], g["col"])))
+    log("results match the oracle on all 45 matrices; timing", args.steps, "steps")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    map_ms = sum(e0.elapsed_time(e1) for evs in ev for e0, e1 in evs)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = cells * args.steps / elapsed / 1e9
+    map_launches = len(mats) * args.steps
+    map_avg_ms = map_ms / map_launches
+    map_bytes_avg = MAP_BYTES_PER_CELL * cells / len(mats)
+    achieved = map_bytes_avg / (map_avg_ms * 1e-3) / 1e9
+    log("step %.3f ms, %.1f Gcells/s; dp-map avg %.1f us -> %.0f GB/s"
+        % (ms_per_step, value, map_avg_ms * 1e3, achieved))
+
+    # spot-check one map against the oracle-derived invariant max(dp) == S
+    for i in (0, len(mats) - 1):
+        if int(DP[i].max().item()) != int(res[i][0]):
+            raise SystemExit("dp map maximum differs from the side on matrix %d" % i)
+
+    extra = {}
+    if not args.no_batched:
+        items = [(B[i], mats[i][0][0]) for i in range(len(mats))]
+        batch = M.Batch(items, ctx=ctx)
+        for _ in range(3):
+            batch.run(stream)
+        torch.cuda.synchronize()
+        got = batch.out[: len(mats)].cpu().numpy()
+        if not np.array_equal(got, res):
+            raise SystemExit("batched results differ from the per-matrix results")
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            batch.run(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_b = e0.elapsed_time(e1) / reps
+        e0.record(stream)
+        for _ in range(reps):
+            for (n, pa, pb, ldw, pdp, pres) in calls:
+                L.ms_max_square(h, pb, n, n, ldw, pres, sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_p = e0.elapsed_time(e1) / reps
+        extra["batched"] = {
+            "what": "largest square of the same 45 packed matrices",
+            "batched_gcells_s": cells / (t_b * 1e-3) / 1e9,
+            "plain_loop_gcells_s": cells / (t_p * 1e-3) / 1e9,
+            "batched_ms": t_b, "plain_loop_ms": t_p,
+        }
+        log("batched %.3f ms vs per-matrix loop %.3f ms" % (t_b, t_p))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gcells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "paper-shaped grid: 45 square Bernoulli(p) matrices, n in "
+                        "{1000,...,5000} x p in {0.1,...,0.9}, seed 10n+10p, uint8 input in HBM; "
+                        "plain per-matrix path: pack + largest square + int32 dp map",
+            "matrices": len(mats),
+            "cells_per_step": cells,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_dpmap (dp-map row pass)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": map_avg_ms * 1e3,
+            "bytes_per_cell": MAP_BYTES_PER_CELL,
+        },
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(mats, args.cpu_budget)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

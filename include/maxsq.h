@@ -117,6 +117,17 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
                         void *stream);
 
 /*
+ * The same dp map when the largest square of this matrix is already on the device: d_max
+ * (device or pinned host memory) must hold the ms_square that ms_max_square wrote for the same
+ * d_bits, m, n; only its side is read, and it sets the bands' and windows' head start, so a
+ * smaller side than the true one gives a wrong map.  Saves the search when both are wanted.
+ * Invalid: as ms_square_map, plus d_max NULL.
+ */
+ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                                 int64_t ld_words, const ms_square *d_max, int32_t *d_dp,
+                                 int64_t ld_dp, void *stream);
+
+/*
  * Many matrices in one go.  h_mats is a host copy of the `count` descriptors whose device
  * copy is d_mats; results go to d_out[0 .. count-1] in the same order.  The work of all
  * matrices is spread over one persistent launch pulling (matrix, tile) items from a device

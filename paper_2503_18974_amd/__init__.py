@@ -22,10 +22,10 @@ from dataclasses import dataclass
 
 __all__ = [
     "MaxsqError", "Square", "lib", "library_path", "ms_create", "ms_destroy", "ms_pack_u8",
-    "ms_max_square", "ms_square_map", "ms_batched_workspace_size", "ms_max_square_batched",
+    "ms_max_square", "ms_square_map", "ms_square_map_from_max", "ms_batched_workspace_size", "ms_max_square_batched",
     "ms_set_config", "ms_get_config", "ms_candidate", "ms_num_candidates", "ms_autotune",
     "ms_autotune_save", "ms_autotune_load", "Context", "pack_u8", "max_square", "square_map",
-    "max_square_batched", "area", "words_per_row",
+    "max_square_batched", "square_map_from_max", "area", "words_per_row",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -90,6 +90,7 @@ def lib():
             "ms_pack_u8": [_P, _P, _I64, _I64, _I64, _P, _I64, _P],
             "ms_max_square": [_P, _P, _I64, _I64, _I64, _P, _P],
             "ms_square_map": [_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P],
+            "ms_square_map_from_max": [_P, _P, _I64, _I64, _I64, _P, _P, _I64, _P],
             "ms_batched_workspace_size": [_P, _P, _I64, ctypes.POINTER(ctypes.c_size_t)],
             "ms_max_square_batched": [_P, _P, _P, _I64, _P, _P, ctypes.c_size_t, _P],
             "ms_candidate": [ctypes.c_int, ctypes.POINTER(_Config)],
@@ -138,6 +139,10 @@ def ms_max_square(ctx, d_bits, m, n, ld_words, d_out, stream) -> int:
 
 def ms_square_map(ctx, d_bits, m, n, ld_words, d_dp, ld_dp, d_out, stream) -> int:
     return lib().ms_square_map(ctx, d_bits, m, n, ld_words, d_dp, ld_dp, d_out, stream)
+
+
+def ms_square_map_from_max(ctx, d_bits, m, n, ld_words, d_max, d_dp, ld_dp, stream) -> int:
+    return lib().ms_square_map_from_max(ctx, d_bits, m, n, ld_words, d_max, d_dp, ld_dp, stream)
 
 
 def ms_batched_workspace_size(ctx, h_mats, count) -> int:
@@ -238,10 +243,16 @@ def _check_bits(bits, n):
     torch = _torch()
     if bits.dtype != torch.int64 or bits.dim() != 2 or not bits.is_cuda:
         raise ValueError("packed bits must be a 2-D int64 CUDA tensor")
+    if bits.size(0) == 0 or n == 0:
+        return
     if bits.stride(1) != 1:
         raise ValueError("packed rows must be contiguous")
     if bits.size(1) < words_per_row(n):
         raise ValueError("packed rows are shorter than ceil(n/64) words")
+
+
+def _ld_words(bits, n) -> int:
+    return bits.stride(0) if (bits.size(0) and n) else max(words_per_row(n), 0)
 
 
 def pack_u8(a, ld_words: int | None = None, ctx=None, stream=None):
@@ -266,7 +277,7 @@ def max_square(bits, n: int, ctx=None, stream=None, out=None, sync: bool = True)
     _check_bits(bits, n)
     m = bits.size(0)
     res = torch.empty(3, dtype=torch.int64, device=bits.device) if out is None else out
-    _check(ms_max_square(_ctx(ctx), bits.data_ptr(), m, n, bits.stride(0), res.data_ptr(),
+    _check(ms_max_square(_ctx(ctx), bits.data_ptr(), m, n, _ld_words(bits, n), res.data_ptr(),
                          _stream(stream)), "ms_max_square")
     if not sync:
         return res
@@ -282,13 +293,28 @@ def square_map(bits, n: int, ctx=None, stream=None, out=None, dp=None, sync: boo
     if dp is None:
         dp = torch.empty((m, n), dtype=torch.int32, device=bits.device)
     res = torch.empty(3, dtype=torch.int64, device=bits.device) if out is None else out
-    _check(ms_square_map(_ctx(ctx), bits.data_ptr(), m, n, bits.stride(0), dp.data_ptr(),
+    _check(ms_square_map(_ctx(ctx), bits.data_ptr(), m, n, _ld_words(bits, n), dp.data_ptr(),
                          dp.stride(0) if dp.numel() else max(n, 1), res.data_ptr(),
                          _stream(stream)), "ms_square_map")
     if not sync:
         return dp, res
     v = res.cpu().tolist()
     return dp, Square(int(v[0]), int(v[1]), int(v[2]))
+
+
+def square_map_from_max(bits, n: int, result, ctx=None, stream=None, dp=None):
+    """dp map given the int64 (3,) device tensor that max_square(..., sync=False) returned for
+    the same bits (skips the second search)."""
+    torch = _torch()
+    _check_bits(bits, n)
+    m = bits.size(0)
+    if dp is None:
+        dp = torch.empty((m, n), dtype=torch.int32, device=bits.device)
+    _check(ms_square_map_from_max(_ctx(ctx), bits.data_ptr(), m, n, _ld_words(bits, n),
+                                  result.data_ptr(), dp.data_ptr(),
+                                  dp.stride(0) if dp.numel() else max(n, 1), _stream(stream)),
+           "ms_square_map_from_max")
+    return dp
 
 
 class Batch:
@@ -305,7 +331,7 @@ class Batch:
         for i, (bits, n) in enumerate(self.items):
             _check_bits(bits, n)
             dev = bits.device
-            self.h_mats[i] = _Matrix(bits.data_ptr(), bits.size(0), int(n), bits.stride(0))
+            self.h_mats[i] = _Matrix(bits.data_ptr(), bits.size(0), int(n), _ld_words(bits, n))
         dev = dev or torch.device("cuda")
         raw = bytes(self.h_mats)[: ctypes.sizeof(_Matrix) * count]
         self.d_mats = torch.frombuffer(bytearray(raw) or bytearray(1), dtype=torch.uint8).to(dev)
@@ -321,7 +347,10 @@ class Batch:
         return self.out[: self.count]
 
     def results(self):
-        return [Square(*map(int, r)) for r in self.out[: self.count].cpu().tolist()]
+        rows = self.out[: self.count].cpu().tolist()
+        if any(r[0] < 0 for r in rows):
+            raise MaxsqError(4, "ms_max_square_batched (device reported an inconsistent batch)")
+        return [Square(*map(int, r)) for r in rows]
 
 
 def max_square_batched(items, ctx=None, stream=None):

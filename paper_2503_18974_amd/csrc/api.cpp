@@ -300,8 +300,33 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
     if (s != MS_OK || m == 0 || n == 0) return s;
     mshost::LaunchEnv env{c->num_cus, st};
     hipError_t e = mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m, n,
-                                             ld_words, d_dp, ld_dp, hdr_of(c), state_of(c));
+                                             ld_words, d_dp, ld_dp, &hdr_of(c)->result,
+                                             state_of(c));
     return hip_status(e);
+}
+
+ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                                 int64_t ld_words, const ms_square *d_max, int32_t *d_dp,
+                                 int64_t ld_dp, void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (ld_dp < 0 || !d_max) return MS_ERR_INVALID_ARGUMENT;
+    if (m > 0 && n > 0) {
+        if (!d_dp || ld_dp < n || mul_overflows(m, ld_dp)) return MS_ERR_INVALID_ARGUMENT;
+    }
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    if (m == 0 || n == 0) return MS_OK;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const ms_config cfg = config_for(c, m, n);
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    s = ensure_scratch(c, m, n, cfg.probe_variant, st);
+    if (s != MS_OK) return s;
+    mshost::LaunchEnv env{c->num_cus, st};
+    return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m,
+                                                n, ld_words, d_dp, ld_dp, d_max, state_of(c)));
 }
 
 ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_t count,
@@ -338,8 +363,8 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
     if (workspace_bytes < L.total) return MS_ERR_WORKSPACE_TOO_SMALL;
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
     hipStream_t st = (hipStream_t)stream;
-    const char *ng = std::getenv("MAXSQ_NO_GRAPH");
-    if (ng && ng[0] == '1') {
+    const char *gv = std::getenv("MAXSQ_GRAPH");
+    if (!(gv && gv[0] == '1')) {
         mshost::LaunchEnv env{c->num_cus, st};
         return hip_status(mshost::launch_batched(env, variant, d_mats, count, d_out, d_workspace, L));
     }
@@ -469,7 +494,8 @@ ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                 mshost::LaunchEnv env{c->num_cus, st};
                 return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows,
                                                             d_bits, m, n, ld_words, d_dp_scratch,
-                                                            ld_dp, hdr_of(c), state_of(c)));
+                                                            ld_dp, &hdr_of(c)->result,
+                                                            state_of(c)));
             }, &t);
             if (s == MS_OK && t < best_map) {
                 best_map = t;

@@ -95,16 +95,27 @@ __device__ __forceinline__ Track wave_track(Track t) {
 // columns xh + g * 64 * CPL + l * CPL + t.  Cells with row >= ra and xa <= col < xb are owned:
 // stored into dp (STORE) and/or folded into the per-lane Track (TRACK).
 //
-// Per row and group: the CPL words of the group are read as wave-uniform values to carry the
-// row run W across words and groups; each lane reads its own word for its bits; the value of
-// dp[i-1][c-1] for a lane's first column comes from the lane to its left (previous row), and
-// for lane 0 from the previous group's last column, saved before that group was overwritten.
+// Rows are staged through LDS in chunks: the wave first loads a chunk of the window's packed
+// words (all loads in flight at once), then one lane per row scans that row's words once to get
+// the row run W entering every word, and only then walks the rows.  Per row and group a lane
+// reads its word and its entering run from LDS; dp[i-1][c-1] for its first column comes from
+// the lane to its left (previous row), and for lane 0 from the previous group's last column,
+// saved before that group was overwritten.
 // ----------------------------------------------------------------------------------------------
+constexpr int LDS_WORDS = 1024;  // staged packed words per wave
+
+struct WaveLds {
+    uint64_t *x;   // LDS_WORDS packed words
+    int32_t *c;    // LDS_WORDS entering row runs
+};
+
 template <int NGMAX, int CPL, bool STORE, bool TRACK>
 __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n, int64_t rh,
                       int64_t ra, int64_t rb, int64_t xh, int64_t xa, int64_t xb, int ng,
-                      int32_t *__restrict__ dp, int64_t ld_dp, bool vec_ok, Track &tr) {
+                      int32_t *__restrict__ dp, int64_t ld_dp, bool vec_ok, Track &tr,
+                      WaveLds lds) {
     static_assert(CPL == 4 || CPL == 8, "columns per lane");
+    static_assert(NGMAX * CPL <= 64, "window words must fit one wave");
     constexpr int GW = 64 * CPL;  // columns per group
     constexpr int LPW = 64 / CPL; // lanes per word
     const int lane = __lane_id();
@@ -112,6 +123,12 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
     const int b = (lane % LPW) * CPL;   // bit offset of the lane's first column in that word
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
+    const int nww = ng * CPL;                    // window words
+    const int rc_max = LDS_WORDS / nww;          // rows per chunk
+    const int fl_w = lane % nww, fl_r = lane / nww, fl_rpp = 64 / nww;
+    const int64_t fl_word = (xh >> 6) + fl_w;
+    const bool fl_ok = fl_r < fl_rpp && fl_word < nwords;
+    const uint64_t fl_mask = (fl_word == nwords - 1) ? lastmask : ~0ull;
 
     int32_t H[NGMAX][CPL], D[NGMAX][CPL];
 #pragma unroll
@@ -122,83 +139,92 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
             D[g][t] = 0;
         }
 
-    for (int64_t i = rh; i < rb; ++i) {
-        const uint64_t *__restrict__ row = bits + i * ldw;
-        const bool own_row = i >= ra;
-        int32_t wcarry = 0;    // row run of ones ending just left of the group
-        int32_t dleft_old = 0; // previous-row dp just left of the group
+    for (int64_t r0 = rh; r0 < rb; r0 += rc_max) {
+        const int rc = (int)(rb - r0 < rc_max ? rb - r0 : rc_max);
+        // stage the chunk's words
+        for (int r = fl_r; r < rc; r += fl_rpp) {
+            uint64_t v = 0;
+            if (fl_ok) v = bits[(r0 + r) * ldw + fl_word] & fl_mask;
+            if (fl_r < fl_rpp) lds.x[r * nww + fl_w] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // row run entering each word (zero at the window's left edge)
+        for (int r = lane; r < rc; r += WAVE) {
+            int32_t run = 0;
+            for (int w = 0; w < nww; ++w) {
+                const uint64_t v = lds.x[r * nww + w];
+                lds.c[r * nww + w] = run;
+                run = (v == ~0ull) ? run + 64 : leading_ones(v);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int rr = 0; rr < rc; ++rr) {
+            const int64_t i = r0 + rr;
+            const bool own_row = i >= ra;
+            int32_t dleft_old = 0;  // previous-row dp just left of the group
 #pragma unroll
-        for (int g = 0; g < NGMAX; ++g) {
-            if (g < ng) {
-                const int64_t gw0 = (xh >> 6) + (int64_t)g * CPL;
-                int32_t cin[CPL];
-                int32_t c = wcarry;
+            for (int g = 0; g < NGMAX; ++g) {
+                if (g < ng) {
+                    const int widx = rr * nww + g * CPL + q;
+                    const uint64_t x = lds.x[widx];
+                    const int32_t carry = lds.c[widx];
+                    int32_t wrun = carry;
+                    if (b != 0) {
+                        const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
+                        wrun = (lo == b) ? b + carry : lo;
+                    }
+                    const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
+                    int32_t dprev = __shfl_up(D[g][CPL - 1], 1);
+                    if (lane == 0) dprev = dleft_old;
+                    dleft_old = __shfl(D[g][CPL - 1], WAVE - 1);
+                    int32_t w = wrun;
 #pragma unroll
-                for (int k = 0; k < CPL; ++k) {
-                    cin[k] = c;
-                    const uint64_t v = row_word(row, gw0 + k, nwords, lastmask);
-                    c = (v == ~0ull) ? c + 64 : leading_ones(v);
-                }
-                wcarry = c;
-                const uint64_t x = row_word(row, gw0 + q, nwords, lastmask);
-                int32_t carry = cin[0];
+                    for (int t = 0; t < CPL; ++t) {
+                        const int32_t mk = -(int32_t)((nib >> t) & 1u);
+                        const int32_t h = (H[g][t] + 1) & mk;
+                        w = (w + 1) & mk;
+                        const int32_t old = D[g][t];
+                        int32_t d = h < w ? h : w;
+                        d = d < dprev + 1 ? d : dprev + 1;
+                        H[g][t] = h;
+                        D[g][t] = d;
+                        dprev = old;
+                    }
+                    const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
+                    if (own_row) {
+                        if (STORE) {
+                            int32_t *p = dp + i * ld_dp + col;
+                            if (col >= xa && col + CPL <= xb) {
+                                if (vec_ok) {
 #pragma unroll
-                for (int k = 1; k < CPL; ++k) carry = (q == k) ? cin[k] : carry;
-                int32_t wrun = carry;
-                if (b != 0) {
-                    const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
-                    wrun = (lo == b) ? b + carry : lo;
-                }
-                const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
-                int32_t dprev = __shfl_up(D[g][CPL - 1], 1);
-                if (lane == 0) dprev = dleft_old;
-                dleft_old = __shfl(D[g][CPL - 1], WAVE - 1);
-                int32_t w = wrun;
+                                    for (int t = 0; t < CPL; t += 4)
+                                        *reinterpret_cast<int4 *>(p + t) = make_int4(
+                                            D[g][t], D[g][t + 1], D[g][t + 2], D[g][t + 3]);
+                                } else {
 #pragma unroll
-                for (int t = 0; t < CPL; ++t) {
-                    const int32_t mk = -(int32_t)((nib >> t) & 1u);
-                    const int32_t h = (H[g][t] + 1) & mk;
-                    w = (w + 1) & mk;
-                    const int32_t old = D[g][t];
-                    int32_t d = h < w ? h : w;
-                    d = d < dprev + 1 ? d : dprev + 1;
-                    H[g][t] = h;
-                    D[g][t] = d;
-                    dprev = old;
-                }
-                const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
-                if (own_row) {
-                    if (STORE) {
-                        int32_t *p = dp + i * ld_dp + col;
-                        if (col >= xa && col + CPL <= xb) {
-                            if (vec_ok) {
-#pragma unroll
-                                for (int t = 0; t < CPL; t += 4)
-                                    *reinterpret_cast<int4 *>(p + t) =
-                                        make_int4(D[g][t], D[g][t + 1], D[g][t + 2], D[g][t + 3]);
+                                    for (int t = 0; t < CPL; ++t) p[t] = D[g][t];
+                                }
                             } else {
 #pragma unroll
-                                for (int t = 0; t < CPL; ++t) p[t] = D[g][t];
+                                for (int t = 0; t < CPL; ++t)
+                                    if (col + t >= xa && col + t < xb) p[t] = D[g][t];
                             }
-                        } else {
-#pragma unroll
-                            for (int t = 0; t < CPL; ++t)
-                                if (col + t >= xa && col + t < xb) p[t] = D[g][t];
                         }
-                    }
-                    if (TRACK) {
+                        if (TRACK) {
 #pragma unroll
-                        for (int t = 0; t < CPL; ++t) {
-                            const bool own = col + t >= xa && col + t < xb;
-                            if (own && D[g][t] > tr.v) {
-                                tr.v = D[g][t];
-                                tr.pos = i * n + col + t;
+                            for (int t = 0; t < CPL; ++t) {
+                                const bool own = col + t >= xa && col + t < xb;
+                                if (own && D[g][t] > tr.v) {
+                                    tr.v = D[g][t];
+                                    tr.pos = i * n + col + t;
+                                }
                             }
                         }
                     }
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -423,7 +449,7 @@ __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_
 template <int NGMAX, int CPL>
 __device__ bool exact_region(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                              int64_t ra, int64_t rb, int64_t xa, int64_t xb, int64_t kmin,
-                             Track &out) {
+                             Track &out, WaveLds lds) {
     constexpr int64_t WIN = (int64_t)NGMAX * 64 * CPL;
     (void)m;
     int64_t U = 2 * kmin;
@@ -438,7 +464,7 @@ __device__ bool exact_region(const uint64_t *__restrict__ bits, int64_t m, int64
             const int64_t xh_w = xa_w - hc > 0 ? ((xa_w - hc) & ~(int64_t)63) : 0;
             const int ngw = (int)((xb_w - xh_w + 64 * CPL - 1) / (64 * CPL));
             dprun<NGMAX, CPL, false, true>(bits, ldw, n, rh, ra, rb, xh_w, xa_w, xb_w, ngw,
-                                           nullptr, 0, false, tr);
+                                           nullptr, 0, false, tr, lds);
         }
         Track w = wave_track(tr);
         if (w.v <= U) {

@@ -85,6 +85,9 @@ __global__ __launch_bounds__(64) void k_exact(const uint64_t *__restrict__ bits,
                                               int64_t sat_cap, int64_t ntx, int64_t tile_rows,
                                               int64_t kc, int32_t *serial_state,
                                               ms_square *out) {
+    __shared__ uint64_t lx[LDS_WORDS];
+    __shared__ int32_t lc[LDS_WORDS];
+    const WaveLds lds{lx, lc};
     const int lane = __lane_id();
     const uint32_t cnt = load_relaxed_u32(&hdr->sat_count);
     if ((int64_t)cnt > sat_cap) {
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(64) void k_exact(const uint64_t *__restrict__ bits,
             const int64_t xe = xa + mshost::PROBE_TILE_WORDS * 64;
             const int64_t xb = xe < n ? xe : n;
             Track t{0, INT64_MAX};
-            if (exact_region<EX_NG, EX_CPL>(bits, m, n, ldw, ra, rb, xa, xb, kc, t)) {
+            if (exact_region<EX_NG, EX_CPL>(bits, m, n, ldw, ra, rb, xa, xb, kc, t, lds)) {
                 if (lane == 0 && t.v > 0) atomicMax(&hdr->key, make_key(t.v, t.pos));
             } else if (lane == 0) {
                 atomicOr(&hdr->serial_flag, 1u);
@@ -136,12 +139,15 @@ template <int NGMAX, int CPL>
 __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits, int64_t m,
                                                int64_t n, int64_t ldw, int32_t *__restrict__ dp,
                                                int64_t ld_dp,
-                                               const mshost::ScratchHeader *__restrict__ hdr,
+                                               const ms_square *__restrict__ maxsq,
                                                int64_t band_rows, int32_t *serial_state,
                                                int vec_ok) {
     constexpr int64_t GW = 64 * CPL;
     constexpr int64_t WIN = NGMAX * GW;
-    const int64_t S = hdr->result.side;
+    __shared__ uint64_t lx[4][LDS_WORDS];
+    __shared__ int32_t lc[4][LDS_WORDS];
+    const WaveLds lds{lx[threadIdx.x / WAVE], lc[threadIdx.x / WAVE]};
+    const int64_t S = __hip_atomic_load(&maxsq->side, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int64_t hc = (S + 63) & ~(int64_t)63;
     if (hc + 64 > WIN) {
         // too large for a register window: one wave sweeps the whole matrix
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
         const int64_t xh = xa - hc > 0 ? xa - hc : 0;
         const int ngi = (int)((xb - xh + GW - 1) / GW);
         dprun<NGMAX, CPL, true, false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp,
-                                       vec_ok != 0, dummy);
+                                       vec_ok != 0, dummy, lds);
     }
 }
 
@@ -255,6 +261,9 @@ __device__ __forceinline__ int64_t find_matrix(const uint64_t *__restrict__ pref
     return lo;
 }
 
+// Tiles of all matrices in one grid-stride pass; the item count comes from the host (it is
+// computed from the same descriptors), so the loop is bounded by construction.  A mismatch with
+// the device-side prefix marks the whole batch as failed instead of running.
 template <class TS>
 __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restrict__ mats,
                                                        int64_t count,
@@ -262,14 +271,15 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
                                                        const uint64_t *__restrict__ prefix,
                                                        BatchCounters *ctr,
                                                        uint64_t *__restrict__ sat_list,
-                                                       uint64_t sat_cap) {
+                                                       uint64_t sat_cap, uint64_t total) {
     const int lane = __lane_id();
-    const uint64_t total = ctr->total;
-    for (;;) {
-        unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(&ctr->head, 1ull);
-        item = __shfl(item, 0);
-        if (item >= total) return;
+    if (__hip_atomic_load(prefix + count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != total) {
+        if (lane == 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->overflow, 2u);
+        return;
+    }
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+    for (uint64_t item = wave; item < total; item += nwave) {
         const int64_t mi = find_matrix(prefix, count, item);
         const ms_matrix d = mats[mi];
         const int64_t nwords = (d.n + 63) >> 6;
@@ -288,8 +298,12 @@ __global__ __launch_bounds__(64) void k_exact_batched(const ms_matrix *__restric
                                                       const uint64_t *__restrict__ sat_list,
                                                       uint64_t sat_cap, int64_t tile_rows,
                                                       int64_t kc) {
+    __shared__ uint64_t lx[LDS_WORDS];
+    __shared__ int32_t lc[LDS_WORDS];
+    const WaveLds lds{lx, lc};
     const int lane = __lane_id();
     const uint32_t cnt = load_relaxed_u32(&ctr->sat_count);
+    if (load_relaxed_u32(&ctr->overflow) & 2u) return;
     if ((uint64_t)cnt > sat_cap) {
         if (lane == 0 && blockIdx.x == 0) atomicOr(&ctr->overflow, 1u);
         return;
@@ -307,7 +321,7 @@ __global__ __launch_bounds__(64) void k_exact_batched(const ms_matrix *__restric
         const int64_t xe = xa + mshost::PROBE_TILE_WORDS * 64;
         const int64_t xb = xe < d.n ? xe : d.n;
         Track t{0, INT64_MAX};
-        if (exact_region<EX_NG, EX_CPL>(d.bits, d.m, d.n, d.ld_words, ra, rb, xa, xb, kc, t)) {
+        if (exact_region<EX_NG, EX_CPL>(d.bits, d.m, d.n, d.ld_words, ra, rb, xa, xb, kc, t, lds)) {
             if (lane == 0 && t.v > 0) atomicMax(keys + mi, make_key(t.v, t.pos));
         } else if (lane == 0) {
             atomicOr(flags + mi, 1u);
@@ -324,16 +338,22 @@ __global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict_
                                                     const BatchCounters *ctr,
                                                     int32_t *serial_state, ms_square *out) {
     const int lane = __lane_id();
-    const bool overflow = ctr->overflow != 0;
+    const uint32_t ovf = load_relaxed_u32(&ctr->overflow);
+    if (ovf & 2u) {  // inconsistent batch: report every result as failed
+        for (int64_t i = blockIdx.x; i < count; i += gridDim.x)
+            if (lane == 0) out[i] = ms_square{-1, -1, -1};
+        return;
+    }
+    const bool overflow = ovf != 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         const ms_matrix d = mats[i];
-        const bool serial = d.m > 0 && d.n > 0 && (flags[i] || overflow);
-        if (!serial && lane == 0) write_result(keys[i], d.n, out + i);
+        const bool serial = d.m > 0 && d.n > 0 && (load_relaxed_u32(flags + i) || overflow);
+        if (!serial && lane == 0) write_result(load_relaxed(keys + i), d.n, out + i);
     }
     if (blockIdx.x != 0) return;
     for (int64_t i = 0; i < count; ++i) {
         const ms_matrix d = mats[i];
-        if (!(d.m > 0 && d.n > 0 && (flags[i] || overflow))) continue;
+        if (!(d.m > 0 && d.n > 0 && (load_relaxed_u32(flags + i) || overflow))) continue;
         const int64_t nw64 = ((d.n + 63) >> 6) * 64;
         Track tr{0, INT64_MAX};
         serial_dp<false>(d.bits, d.m, d.n, d.ld_words, nullptr, 0, serial_state,
@@ -413,18 +433,18 @@ hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *
 
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
-                             int64_t ld_dp, const ScratchHeader *hdr, int32_t *serial_state) {
+                             int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state) {
     const int vec_ok = ((uintptr_t)dp % 16 == 0) && (ld_dp % 4 == 0);
     const int64_t items_bound = cdiv(m, band_rows) * cdiv(n, 64);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(items_bound, 4),
                                                                    (int64_t)env.num_cus * 8));
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<4, 8>), dim3((unsigned)blocks), dim3(256), 0, env.stream,
-                           bits, m, n, ldw, dp, ld_dp, hdr, (int64_t)band_rows, serial_state,
+                           bits, m, n, ldw, dp, ld_dp, maxsq, (int64_t)band_rows, serial_state,
                            vec_ok);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<8, 4>), dim3((unsigned)blocks), dim3(256), 0, env.stream,
-                           bits, m, n, ldw, dp, ld_dp, hdr, (int64_t)band_rows, serial_state,
+                           bits, m, n, ldw, dp, ld_dp, maxsq, (int64_t)band_rows, serial_state,
                            vec_ok);
     }
     return hipGetLastError();
@@ -460,6 +480,7 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
         maxw = std::max<int64_t>(maxw, cdiv(std::max<int64_t>(h_mats[i].n, 1), 64));
     }
     L.sat_cap = tiles;
+    L.total_tiles = tiles;
     L.max_nwords = maxw;
     size_t off = 0;
     L.counters = off; off = align256(off + sizeof(msk::BatchCounters));
@@ -473,8 +494,8 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
 }
 
 template <class TS>
-static void launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, int64_t count,
-                             ms_square *out, char *ws, const BatchLayout &L) {
+static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, int64_t count,
+                                   ms_square *out, char *ws, const BatchLayout &L) {
     auto *ctr = reinterpret_cast<msk::BatchCounters *>(ws + L.counters);
     auto *keys = reinterpret_cast<unsigned long long *>(ws + L.keys);
     auto *prefix = reinterpret_cast<uint64_t *>(ws + L.prefix);
@@ -483,25 +504,32 @@ static void launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, int64_
     auto *state = reinterpret_cast<int32_t *>(ws + L.serial_state);
     hipLaunchKernelGGL(msk::k_batch_init<TS>, dim3(1), dim3(1024), 0, env.stream, mats, count,
                        keys, prefix, flags, ctr);
-    hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)(env.num_cus * 8)), dim3(256), 0,
-                       env.stream, mats, count, keys, prefix, ctr, sat, L.sat_cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t pblocks = std::max<int64_t>(
+        1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 4), (int64_t)env.num_cus * 8));
+    hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)pblocks), dim3(256), 0,
+                       env.stream, mats, count, keys, prefix, ctr, sat, L.sat_cap,
+                       (uint64_t)L.total_tiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(msk::k_exact_batched, dim3((unsigned)(env.num_cus * 4)), dim3(64), 0,
                        env.stream, mats, keys, flags, ctr, sat, L.sat_cap, (int64_t)TS::TR,
                        (int64_t)TS::KC);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t fb = std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)env.num_cus * 4));
     hipLaunchKernelGGL(msk::k_batch_final, dim3((unsigned)fb), dim3(64), 0, env.stream, mats,
                        count, keys, flags, ctr, state, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_mats,
                           int64_t count, ms_square *out, void *ws, const BatchLayout &L) {
     char *w = static_cast<char *>(ws);
     switch (variant) {
-    case 0: launch_batched_t<TS0>(env, d_mats, count, out, w, L); break;
-    case 1: launch_batched_t<TS1>(env, d_mats, count, out, w, L); break;
-    default: launch_batched_t<TS2>(env, d_mats, count, out, w, L); break;
+    case 0: return launch_batched_t<TS0>(env, d_mats, count, out, w, L);
+    case 1: return launch_batched_t<TS1>(env, d_mats, count, out, w, L);
+    default: return launch_batched_t<TS2>(env, d_mats, count, out, w, L);
     }
-    return hipGetLastError();
 }
 
 } // namespace mshost

@@ -46,10 +46,10 @@ hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *
                              int64_t n, int64_t ldw, ScratchHeader *hdr, uint64_t *sat_list,
                              uint64_t sat_cap, int32_t *serial_state, ms_square *out);
 
-// dp map of one matrix; reads S from hdr->result (written by launch_max_square).
+// dp map of one matrix; reads S from *maxsq on the device (a largest-square result).
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
-                             int64_t ld_dp, const ScratchHeader *hdr, int32_t *serial_state);
+                             int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state);
 
 // Write a constant result (empty matrices).
 hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,
@@ -59,6 +59,7 @@ hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHead
 struct BatchLayout {
     size_t keys, prefix, counters, sat_list, serial_state, flags, total;
     uint64_t sat_cap;
+    uint64_t total_tiles;
     int64_t max_nwords;
 };
 BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count);

@@ -1,0 +1,76 @@
+"""Batched entry point: every result equals the single-matrix call and the oracle, under mixed
+shapes, empty matrices, duplicates and shuffled order."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+import paper_2503_18974_amd as M
+from gpu_util import announce, to_dev_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def make_mix(seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        m = int(np.exp(rng.uniform(np.log(16), np.log(1500))))
+        n = int(np.exp(rng.uniform(np.log(16), np.log(1500))))
+        a = (rng.random((m, n)) < rng.uniform(0.1, 0.95)).astype(np.uint8)
+        if k % 7 == 3:   # planted squares beyond the erosion tile's certified side
+            s = min(m, n, int(rng.integers(17, 200)))
+            r0, c0 = int(rng.integers(0, m - s + 1)), int(rng.integers(0, n - s + 1))
+            a[r0:r0 + s, c0:c0 + s] = 1
+        out.append(a)
+    return out
+
+
+def check_batch(mats, dev):
+    items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
+    got = M.max_square_batched(items)
+    for a, g, (d, n) in zip(mats, got, items):
+        ref = oracle.max_square(a)
+        assert (g.side, g.row, g.col) == ref, (a.shape, g, ref)
+        single = M.max_square(d, n)
+        assert (single.side, single.row, single.col) == ref
+
+
+def test_batched_small_mix(dev):
+    announce("batched mix 40")
+    check_batch(make_mix(1, 40), dev)
+
+
+def test_batched_edges(dev):
+    announce("batched edges")
+    mats = [np.zeros((0, 5), np.uint8), np.ones((1, 1), np.uint8), np.zeros((33, 70), np.uint8),
+            np.ones((300, 200), np.uint8), W.gen_bernoulli(64, 4096, 0.9, 3),
+            np.zeros((5, 0), np.uint8), W.gen_bernoulli(1, 5000, 0.5, 4)]
+    check_batch(mats, dev)
+
+
+def test_batched_large_square_serial_path(dev):
+    """A square wider than the exact pass's window goes through the serial pass."""
+    announce("batched serial")
+    mats = [np.ones((2100, 2050), np.uint8), W.gen_bernoulli(500, 500, 0.7, 5)]
+    check_batch(mats, dev)
+
+
+def test_batched_order_and_duplicates(dev):
+    announce("batched order")
+    mats = make_mix(2, 12)
+    mats = mats + mats[:4]
+    perm = np.random.default_rng(3).permutation(len(mats))
+    check_batch([mats[i] for i in perm], dev)
+
+
+def test_batched_repeat_reuses_workspace(dev):
+    announce("batched repeat")
+    mats = make_mix(4, 20)
+    items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
+    b = M.Batch(items)
+    refs = [oracle.max_square(a) for a in mats]
+    for _ in range(3):
+        b.run()
+        got = b.results()
+        assert [(g.side, g.row, g.col) for g in got] == refs
