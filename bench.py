@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -136,6 +137,29 @@ def main():
     log("step %.3f ms, %.1f Gcells/s; dp-map avg %.1f us -> %.0f GB/s"
         % (ms_per_step, value, map_avg_ms * 1e3, achieved))
 
+    # the same step recorded once into a graph and replayed (same kernels, one submission)
+    graph_value = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            gs = torch.cuda.current_stream()
+            for (n, pa, pb, ldw, pdp, pres) in calls:
+                L.ms_pack_u8(h, pa, n, n, n, pb, ldw, gs.cuda_stream)
+                L.ms_max_square(h, pb, n, n, ldw, pres, gs.cuda_stream)
+                L.ms_square_map_from_max(h, pb, n, n, ldw, pres, pdp, n, gs.cuda_stream)
+        RES.fill_(-9)
+        g.replay()
+        torch.cuda.synchronize()
+        if not np.array_equal(RES.cpu().numpy(), res):
+            raise SystemExit("graph-replayed step gives different results")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_value = cells * args.steps / (time.perf_counter() - t0) / 1e9
+        log("graph-replayed step: %.1f Gcells/s" % graph_value)
+
     # spot-check one map against the oracle-derived invariant max(dp) == S
     for i in (0, len(mats) - 1):
         if int(DP[i].max().item()) != int(res[i][0]):
@@ -206,6 +230,8 @@ def main():
             "bytes_per_cell": MAP_BYTES_PER_CELL,
         },
     }
+    if graph_value is not None:
+        extra["graph_step_gcells_s"] = graph_value
     out.update(extra)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)

@@ -40,9 +40,8 @@ struct GraphEntry {
 struct ms_ctx {
     int device = 0;
     int num_cus = 256;
-    // single-matrix scratch: header | saturated-tile list | serial-pass state
+    // single-matrix scratch: header | serial-pass state
     void *scratch = nullptr;
-    uint64_t sat_cap = 0;
     int64_t state_words = 0;
     bool dirty = false;
     bool has_forced = false;
@@ -127,12 +126,10 @@ bool config_valid(const ms_config &cfg) {
            cfg.map_band_rows <= (1 << 20);
 }
 
-// Make sure the context scratch holds the tile list and serial state for an m x n matrix.
-ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, int variant, hipStream_t stream) {
+// Make sure the context scratch holds the serial-pass state for an m x n matrix.
+ms_status ensure_scratch(ms_ctx *c, int64_t n, hipStream_t stream) {
     const int64_t nwords = std::max<int64_t>(1, cdiv(n, 64));
-    const uint64_t tiles = (uint64_t)(cdiv(std::max<int64_t>(m, 1), mshost::probe_tile_rows(variant)) *
-                                      cdiv(nwords, mshost::PROBE_TILE_WORDS));
-    if (c->scratch && c->sat_cap >= tiles && c->state_words >= nwords) {
+    if (c->scratch && c->state_words >= nwords) {
         if (c->dirty) {
             if (hipMemsetAsync(c->scratch, 0, sizeof(mshost::ScratchHeader), stream) != hipSuccess)
                 return MS_ERR_HIP;
@@ -140,10 +137,8 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, int variant, hipStream
         }
         return MS_OK;
     }
-    const uint64_t cap = std::max<uint64_t>(tiles, c->sat_cap) + 1024;
     const int64_t words = std::max<int64_t>(nwords, c->state_words);
-    const size_t bytes = sizeof(mshost::ScratchHeader) + cap * sizeof(uint64_t) +
-                         (size_t)words * 64 * 2 * sizeof(int32_t);
+    const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t);
     if (c->scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
@@ -157,18 +152,16 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, int variant, hipStream
         return MS_ERR_HIP;
     }
     c->scratch = p;
-    c->sat_cap = cap;
     c->state_words = words;
     c->dirty = false;
     return MS_OK;
 }
 
 mshost::ScratchHeader *hdr_of(ms_ctx *c) { return static_cast<mshost::ScratchHeader *>(c->scratch); }
-uint64_t *sat_of(ms_ctx *c) {
-    return reinterpret_cast<uint64_t *>(static_cast<char *>(c->scratch) +
-                                        sizeof(mshost::ScratchHeader));
+int32_t *state_of(ms_ctx *c) {
+    return reinterpret_cast<int32_t *>(static_cast<char *>(c->scratch) +
+                                       sizeof(mshost::ScratchHeader));
 }
-int32_t *state_of(ms_ctx *c) { return reinterpret_cast<int32_t *>(sat_of(c) + c->sat_cap); }
 
 ms_status validate_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t ldw) {
     if (m < 0 || n < 0 || ldw < 0) return MS_ERR_INVALID_ARGUMENT;
@@ -184,7 +177,7 @@ ms_status validate_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t ld
 ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, int64_t m,
                          int64_t n, int64_t ldw, ms_square *out, hipStream_t stream) {
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
-    ms_status s = ensure_scratch(c, m, n, cfg.probe_variant, stream);
+    ms_status s = ensure_scratch(c, n, stream);
     if (s != MS_OK) return s;
     mshost::LaunchEnv env{c->num_cus, stream};
     hipError_t e;
@@ -192,7 +185,7 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
         e = mshost::launch_write_result(env, out, hdr_of(c), out ? 1 : 0);
     } else {
         e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
-                                      sat_of(c), c->sat_cap, state_of(c), out);
+                                      state_of(c), out);
     }
     if (e != hipSuccess) {
         c->dirty = true;
@@ -322,7 +315,7 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
     const ms_config cfg = config_for(c, m, n);
     hipStream_t st = (hipStream_t)stream;
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
-    s = ensure_scratch(c, m, n, cfg.probe_variant, st);
+    s = ensure_scratch(c, n, st);
     if (s != MS_OK) return s;
     mshost::LaunchEnv env{c->num_cus, st};
     return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m,

@@ -75,6 +75,17 @@ __device__ __forceinline__ int32_t leading_ones(uint64_t v) {
     return (v == ~0ull) ? 64 : (int32_t)__clzll(~v);
 }
 
+// Lane l receives lane l-1's value, lane 0 receives `first` (DPP wave_shr:1).
+__device__ __forceinline__ int32_t from_left_lane(int32_t v, int32_t first) {
+    return __builtin_amdgcn_update_dpp(first, v, 0x138, 0xf, 0xf, false);
+}
+
+// Within each row of 16 lanes, lane l receives lane l-1's value; the first lane of every row
+// receives 0 (DPP row_shr:1 with bound control).
+__device__ __forceinline__ uint32_t from_left_in_row16(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x111, 0xf, 0xf, true);
+}
+
 // Per-lane running maximum with the first row-major position (for the tracking mode).
 struct Track {
     int32_t v;
@@ -158,25 +169,47 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // the words and entering runs of the next row are read before the current row is used
+        uint64_t nx[NGMAX];
+        int32_t ncr[NGMAX];
+#pragma unroll
+        for (int g = 0; g < NGMAX; ++g) {
+            nx[g] = (g < ng) ? lds.x[g * CPL + q] : 0ull;
+            ncr[g] = (g < ng) ? lds.c[g * CPL + q] : 0;
+        }
         for (int rr = 0; rr < rc; ++rr) {
             const int64_t i = r0 + rr;
             const bool own_row = i >= ra;
+            uint64_t cx[NGMAX];
+            int32_t ccr[NGMAX];
+#pragma unroll
+            for (int g = 0; g < NGMAX; ++g) {
+                cx[g] = nx[g];
+                ccr[g] = ncr[g];
+            }
+            if (rr + 1 < rc) {
+#pragma unroll
+                for (int g = 0; g < NGMAX; ++g) {
+                    if (g < ng) {
+                        nx[g] = lds.x[(rr + 1) * nww + g * CPL + q];
+                        ncr[g] = lds.c[(rr + 1) * nww + g * CPL + q];
+                    }
+                }
+            }
             int32_t dleft_old = 0;  // previous-row dp just left of the group
 #pragma unroll
             for (int g = 0; g < NGMAX; ++g) {
                 if (g < ng) {
-                    const int widx = rr * nww + g * CPL + q;
-                    const uint64_t x = lds.x[widx];
-                    const int32_t carry = lds.c[widx];
+                    const uint64_t x = cx[g];
+                    const int32_t carry = ccr[g];
                     int32_t wrun = carry;
                     if (b != 0) {
                         const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
                         wrun = (lo == b) ? b + carry : lo;
                     }
                     const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
-                    int32_t dprev = __shfl_up(D[g][CPL - 1], 1);
-                    if (lane == 0) dprev = dleft_old;
-                    dleft_old = __shfl(D[g][CPL - 1], WAVE - 1);
+                    int32_t dprev = from_left_lane(D[g][CPL - 1], dleft_old);
+                    dleft_old = __builtin_amdgcn_readlane(D[g][CPL - 1], WAVE - 1);
                     int32_t w = wrun;
 #pragma unroll
                     for (int t = 0; t < CPL; ++t) {
@@ -331,8 +364,7 @@ __device__ __forceinline__ void erode(const uint64_t (&E)[RPL], uint64_t (&T)[RP
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const uint64_t f = T[r];
-        uint32_t lh = __shfl_up((uint32_t)(f >> 32), 1, 16);
-        lh = wl ? lh : 0u;
+        const uint32_t lh = from_left_in_row16((uint32_t)(f >> 32));
         T[r] = f & ((f << D) | (uint64_t)(lh >> (32 - D)));
     }
 }
@@ -363,84 +395,15 @@ __device__ __forceinline__ bool any_owned(const uint64_t (&T)[TS::RPL], int rg, 
     return __ballot(lane_ok && acc != 0) != 0;
 }
 
+constexpr int EX_NG = 8;    // exact pass window: 8 groups x 256 columns
+constexpr int EX_CPL = 4;
+
 // Where the outcome of one tile goes.
 struct TileSink {
     unsigned long long *key;   // atomicMax target
-    uint32_t *sat_count;       // saturated-tile queue
-    uint64_t *sat_list;
-    uint64_t sat_cap;
-    uint64_t sat_tag;          // high bits stored with the tile id (matrix index when batched)
+    uint32_t *serial_flag;     // set when a square is too wide for the exact pass's window
+    WaveLds lds;               // this wave's LDS staging area (exact pass)
 };
-
-// Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
-// key with the first owned cell of E_k; a tile whose E_KC is non-empty is "saturated" and queued.
-template <class TS>
-__device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
-                            int64_t ty, int64_t tx, int64_t tile_id, const TileSink &sink) {
-    constexpr int RPL = TS::RPL;
-    const int lane = __lane_id();
-    const int wl = lane & 15, rg = lane >> 4;
-    const int64_t nwords = (n + 63) >> 6;
-    const int64_t tile_r0 = ty * TS::TR - TS::HALO;
-    const int64_t wlane = tx * TS::OWN_WORDS - 1 + wl;
-    const bool wvalid = wlane >= 0 && wlane < nwords;
-    const uint64_t wmask = (wlane == nwords - 1) ? last_word_mask(n) : ~0ull;
-    uint64_t E[RPL], T[RPL];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int64_t row = tile_r0 + rg * RPL + r;
-        E[r] = (wvalid && row >= 0 && row < m) ? (bits[row * ldw + wlane] & wmask) : 0ull;
-    }
-    const bool lane_ok = wl != 0 && wvalid;
-    if (!any_owned<TS>(E, rg, lane_ok)) return;
-
-    int cur = 1;
-    bool saturated = true;
-    while (cur < TS::KC) {
-        erode_by<RPL>(E, T, cur, rg, wl);
-        if (any_owned<TS>(T, rg, lane_ok)) {
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) E[r] = T[r];
-            cur <<= 1;
-        } else {
-            saturated = false;
-            break;
-        }
-    }
-    if (!saturated) {
-        // the tile's side is in [cur, 2 cur - 1]; skip it if it cannot reach the best so far
-        int64_t best = key_side(load_relaxed(sink.key));
-        if (2 * cur - 1 < best) return;
-        for (int d = cur >> 1; d >= 1; d >>= 1) {
-            erode_by<RPL>(E, T, d, rg, wl);
-            if (any_owned<TS>(T, rg, lane_ok)) {
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) E[r] = T[r];
-                cur += d;
-            }
-            if (cur + d - 1 < best) return;
-        }
-        if (cur < best) return;
-    }
-    // first owned cell of E_cur in row-major order
-    int64_t pos = INT64_MAX;
-    if (lane_ok) {
-#pragma unroll
-        for (int r = RPL - 1; r >= 0; --r) {
-            const bool owned = rg || r >= TS::HALO;
-            const int64_t row = tile_r0 + rg * RPL + r;
-            if (owned && E[r]) pos = row * n + wlane * 64 + (__ffsll((long long)E[r]) - 1);
-        }
-    }
-    pos = wave_min_i64(pos);
-    if (lane == 0) {
-        atomicMax(sink.key, make_key(cur, pos));
-        if (saturated) {
-            const uint32_t slot = atomicAdd(sink.sat_count, 1u);
-            if (slot < sink.sat_cap) sink.sat_list[slot] = sink.sat_tag | (uint64_t)tile_id;
-        }
-    }
-}
 
 // Exact largest square among the owned cells [ra, rb) x [xa, xb) of a saturated tile (whose
 // side is known to be >= kmin): dprun with a halo U that doubles until the local maximum M
@@ -472,6 +435,86 @@ __device__ bool exact_region(const uint64_t *__restrict__ bits, int64_t m, int64
             return true;
         }
         U = 2 * (int64_t)w.v;
+    }
+}
+
+
+// Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
+// key with the first owned cell of E_k.  A tile whose E_KC is non-empty is "saturated": its
+// exact side comes from the dp pass with a doubling halo, run by the same wave.
+template <class TS>
+__device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                            int64_t ty, int64_t tx, const TileSink &sink) {
+    constexpr int RPL = TS::RPL;
+    const int lane = __lane_id();
+    const int wl = lane & 15, rg = lane >> 4;
+    const int64_t nwords = (n + 63) >> 6;
+    const int64_t tile_r0 = ty * TS::TR - TS::HALO;
+    const int64_t wlane = tx * TS::OWN_WORDS - 1 + wl;
+    const bool wvalid = wlane >= 0 && wlane < nwords;
+    const uint64_t wmask = (wlane == nwords - 1) ? last_word_mask(n) : ~0ull;
+    uint64_t E[RPL], T[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int64_t row = tile_r0 + rg * RPL + r;
+        E[r] = (wvalid && row >= 0 && row < m) ? (bits[row * ldw + wlane] & wmask) : 0ull;
+    }
+    const bool lane_ok = wl != 0 && wvalid;
+    // best side found so far by any tile (read now so the load overlaps the erosion steps)
+    const int64_t best = key_side(load_relaxed(sink.key));
+    if (!any_owned<TS>(E, rg, lane_ok)) return;
+
+    int cur = 1;
+    bool saturated = true;
+    while (cur < TS::KC) {
+        erode_by<RPL>(E, T, cur, rg, wl);
+        if (any_owned<TS>(T, rg, lane_ok)) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) E[r] = T[r];
+            cur <<= 1;
+        } else {
+            saturated = false;
+            break;
+        }
+    }
+    if (!saturated) {
+        // the tile's side is in [cur, 2 cur - 1]; skip it if it cannot reach the best so far
+        if (2 * cur - 1 < best) return;
+        for (int d = cur >> 1; d >= 1; d >>= 1) {
+            erode_by<RPL>(E, T, d, rg, wl);
+            if (any_owned<TS>(T, rg, lane_ok)) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) E[r] = T[r];
+                cur += d;
+            }
+            if (cur + d - 1 < best) return;
+        }
+        if (cur < best) return;
+    }
+    // first owned cell of E_cur in row-major order
+    int64_t pos = INT64_MAX;
+    if (lane_ok) {
+#pragma unroll
+        for (int r = RPL - 1; r >= 0; --r) {
+            const bool owned = rg || r >= TS::HALO;
+            const int64_t row = tile_r0 + rg * RPL + r;
+            if (owned && E[r]) pos = row * n + wlane * 64 + (__ffsll((long long)E[r]) - 1);
+        }
+    }
+    pos = wave_min_i64(pos);
+    if (lane == 0) atomicMax(sink.key, make_key(cur, pos));
+    if (saturated) {
+        // the tile holds a square of side KC or more: its exact side and first corner come from
+        // the windowed dp pass over its owned cells
+        const int64_t ra = ty * TS::TR, rb = ra + TS::TR < m ? ra + TS::TR : m;
+        const int64_t xa = tx * TS::OWN_WORDS * 64;
+        const int64_t xb = xa + TS::OWN_WORDS * 64 < n ? xa + TS::OWN_WORDS * 64 : n;
+        Track t{0, INT64_MAX};
+        if (exact_region<EX_NG, EX_CPL>(bits, m, n, ldw, ra, rb, xa, xb, TS::KC, t, sink.lds)) {
+            if (lane == 0 && t.v > 0) atomicMax(sink.key, make_key(t.v, t.pos));
+        } else if (lane == 0) {
+            atomicOr(sink.serial_flag, 1u);
+        }
     }
 }
 

@@ -1,16 +1,17 @@
 // kernels.hip -- libmaxsq kernels for gfx950 and their host launchers.
 //
 // Single matrix, largest square (two launches):
-//   k_probe    : erosion search over register tiles (device.hpp tile_search); each tile pushes
-//                its exact side (if below the tile's certified bound) with its first corner into
-//                one atomic key, or queues itself as saturated.
-//   k_exact    : saturated tiles get their exact side from the windowed dp pass with a doubling
-//                halo; the last wave to finish turns the key into the result and clears the
-//                scratch for the next call.
+//   k_probe    : erosion search over register tiles (device.hpp tile_search).  Each tile pushes
+//                its exact side with its first corner into one atomic key; a tile holding a
+//                square beyond its certified side runs the windowed dp pass on its own cells.
+//   k_finalize : one wave turns the key into the result (or, for a square too wide for any
+//                window, runs the serial pass) and clears the scratch for the next call.
 // dp map (one more launch): k_dpmap reads S on the device and covers the matrix with row bands
 // and column windows that start S rows / columns early (zero state there is exact).
-// Batched: k_batch_init (prefix of tile counts, clear keys), k_probe_batched (one persistent
-// grid pulling (matrix, tile) items from an atomic queue), k_exact_batched, k_batch_final.
+// Batched: k_batch_init (prefix of tile counts, clear keys), k_probe_batched (every tile of every
+// matrix in one grid-stride pass), k_batch_final (key -> result per matrix).
+#include <algorithm>
+
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -24,27 +25,65 @@ __device__ __forceinline__ uint32_t nz4(uint32_t x) {
     return (t * 0x00204081u) >> 28;
 }
 
+// Load 16 bytes starting at p, using the widest loads that ALIGN (a power of two dividing the
+// address) allows.
+template <int ALIGN>
+__device__ __forceinline__ uint4 load16(const uint8_t *__restrict__ p) {
+    if constexpr (ALIGN >= 16) {
+        return *reinterpret_cast<const uint4 *>(p);
+    } else if constexpr (ALIGN == 8) {
+        const uint2 a = reinterpret_cast<const uint2 *>(p)[0];
+        const uint2 b = reinterpret_cast<const uint2 *>(p)[1];
+        return make_uint4(a.x, a.y, b.x, b.y);
+    } else if constexpr (ALIGN == 4) {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+        return make_uint4(q[0], q[1], q[2], q[3]);
+    } else {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            w[k] = (uint32_t)p[4 * k] | ((uint32_t)p[4 * k + 1] << 8) |
+                   ((uint32_t)p[4 * k + 2] << 16) | ((uint32_t)p[4 * k + 3] << 24);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// One packed word (64 columns) per thread: four 16-byte loads in flight, one 8-byte store.
+// Row starts are ALIGN-byte aligned (ALIGN divides both the base address and ld_bytes).
+template <int ALIGN>
 __global__ __launch_bounds__(256) void k_pack_u8(const uint8_t *__restrict__ a, int64_t m,
                                                  int64_t n, int64_t ldb,
-                                                 uint64_t *__restrict__ bits, int64_t ldw,
-                                                 int aligned) {
-    const int64_t groups = 4 * ((n + 63) >> 6);  // 16-column groups of the valid words
-    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
-        const uint8_t *__restrict__ src = a + i * ldb;
-        uint16_t *__restrict__ dst = reinterpret_cast<uint16_t *>(bits + i * ldw);
-        for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
-             g += (int64_t)gridDim.x * blockDim.x) {
-            const int64_t c = g * 16;
-            uint32_t mask = 0;
-            if (aligned && c + 16 <= n) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(src + c);
-                mask = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
-            } else {
-                for (int t = 0; t < 16; ++t)
-                    if (c + t < n && src[c + t] != 0) mask |= 1u << t;
-            }
-            dst[g] = (uint16_t)mask;
+                                                 uint64_t *__restrict__ bits, int64_t ldw) {
+    const int64_t nwords = (n + 63) >> 6;
+    const int64_t total = m * nwords;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t row, w;
+        if (total <= 0xFFFFFFFFll) {
+            row = (uint32_t)t / (uint32_t)nwords;
+            w = (uint32_t)t - (uint32_t)row * (uint32_t)nwords;
+        } else {
+            row = t / nwords;
+            w = t - row * nwords;
         }
+        const uint8_t *__restrict__ src = a + row * ldb + w * 64;
+        uint64_t word = 0;
+        if ((w + 1) * 64 <= n) {
+            uint4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = load16<ALIGN>(src + 16 * k);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t m16 = nz4(v[k].x) | (nz4(v[k].y) << 4) | (nz4(v[k].z) << 8) |
+                                     (nz4(v[k].w) << 12);
+                word |= (uint64_t)m16 << (16 * k);
+            }
+        } else {
+            const int64_t rem = n - w * 64;
+            for (int64_t k = 0; k < rem; ++k)
+                if (src[k] != 0) word |= 1ull << k;
+        }
+        bits[row * ldw + w] = word;
     }
 }
 
@@ -52,17 +91,18 @@ __global__ __launch_bounds__(256) void k_pack_u8(const uint8_t *__restrict__ a, 
 template <class TS>
 __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits, int64_t m,
                                                int64_t n, int64_t ldw, int64_t ntiles,
-                                               int64_t ntx, TileSink sink) {
+                                               int64_t ntx, mshost::ScratchHeader *hdr) {
+    __shared__ uint64_t lx[4][LDS_WORDS];
+    __shared__ int32_t lc[4][LDS_WORDS];
+    const int wib = threadIdx.x / WAVE;
+    const TileSink sink{&hdr->key, &hdr->serial_flag, WaveLds{lx[wib], lc[wib]}};
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     for (int64_t t = wave; t < ntiles; t += nwave) {
         const int64_t ty = t / ntx, tx = t - ty * ntx;
-        tile_search<TS>(bits, m, n, ldw, ty, tx, t, sink);
+        tile_search<TS>(bits, m, n, ldw, ty, tx, sink);
     }
 }
-
-constexpr int EX_NG = 8;   // exact pass window: 8 groups x 256 columns
-constexpr int EX_CPL = 4;
 
 __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) {
     ms_square r;
@@ -78,63 +118,34 @@ __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) 
     *dst = r;
 }
 
-__global__ __launch_bounds__(64) void k_exact(const uint64_t *__restrict__ bits, int64_t m,
-                                              int64_t n, int64_t ldw,
-                                              mshost::ScratchHeader *hdr,
-                                              const uint64_t *__restrict__ sat_list,
-                                              int64_t sat_cap, int64_t ntx, int64_t tile_rows,
-                                              int64_t kc, int32_t *serial_state,
-                                              ms_square *out) {
-    __shared__ uint64_t lx[LDS_WORDS];
-    __shared__ int32_t lc[LDS_WORDS];
-    const WaveLds lds{lx, lc};
+// One wave: key -> result (serial pass if a square was too wide for the windowed pass), then
+// clear the scratch.
+__global__ __launch_bounds__(64) void k_finalize(const uint64_t *__restrict__ bits, int64_t m,
+                                                 int64_t n, int64_t ldw,
+                                                 mshost::ScratchHeader *hdr,
+                                                 int32_t *serial_state, ms_square *out) {
     const int lane = __lane_id();
-    const uint32_t cnt = load_relaxed_u32(&hdr->sat_count);
-    if ((int64_t)cnt > sat_cap) {
-        if (lane == 0 && blockIdx.x == 0) atomicOr(&hdr->serial_flag, 1u);
-    } else {
-        for (int64_t s = blockIdx.x; s < (int64_t)cnt; s += gridDim.x) {
-            const int64_t tid = (int64_t)(sat_list[s] & 0xFFFFFFFFFFFFull);
-            const int64_t ty = tid / ntx, tx = tid - ty * ntx;
-            const int64_t ra = ty * tile_rows, rb = ra + tile_rows < m ? ra + tile_rows : m;
-            const int64_t xa = tx * mshost::PROBE_TILE_WORDS * 64;
-            const int64_t xe = xa + mshost::PROBE_TILE_WORDS * 64;
-            const int64_t xb = xe < n ? xe : n;
-            Track t{0, INT64_MAX};
-            if (exact_region<EX_NG, EX_CPL>(bits, m, n, ldw, ra, rb, xa, xb, kc, t, lds)) {
-                if (lane == 0 && t.v > 0) atomicMax(&hdr->key, make_key(t.v, t.pos));
-            } else if (lane == 0) {
-                atomicOr(&hdr->serial_flag, 1u);
-            }
-        }
-    }
-    __threadfence();
-    uint32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(&hdr->done, 1u);
-    prev = __shfl(prev, 0);
-    if (prev != gridDim.x - 1) return;
-    __threadfence();
     unsigned long long key;
-    if (__hip_atomic_load(&hdr->serial_flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (load_relaxed_u32(&hdr->serial_flag)) {
         const int64_t nw64 = ((n + 63) >> 6) * 64;
         Track tr{0, INT64_MAX};
         serial_dp<false>(bits, m, n, ldw, nullptr, 0, serial_state, serial_state + nw64, tr);
         const Track w = wave_track(tr);
         key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
     } else {
-        key = __hip_atomic_load(&hdr->key, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        key = load_relaxed(&hdr->key);
     }
     if (lane == 0) {
         write_result(key, n, &hdr->result);
         if (out) write_result(key, n, out);
         hdr->key = 0;
-        hdr->sat_count = 0;
-        hdr->done = 0;
         hdr->serial_flag = 0;
     }
 }
 
 // ---------------------------------------------------------------------------------- map
+// Band height: at least band_rows and 4 S (so the S-row head start costs at most a quarter),
+// halved while that leaves fewer items than waves, down to 2 S (or 16 rows).
 template <int NGMAX, int CPL>
 __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits, int64_t m,
                                                int64_t n, int64_t ldw, int32_t *__restrict__ dp,
@@ -161,12 +172,14 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
     int64_t ng = (hc + (4 * hc > 256 ? 4 * hc : 256) + GW - 1) / GW;
     ng = ng < 1 ? 1 : (ng > NGMAX ? NGMAX : ng);
     const int64_t ow = ng * GW - hc;
-    int64_t R = band_rows > 4 * S ? band_rows : 4 * S;
-    R = R < m ? R : m;
     const int64_t nwin = (n + ow - 1) / ow;
-    const int64_t items = ((m + R - 1) / R) * nwin;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    int64_t R = band_rows > 4 * S ? band_rows : 4 * S;
+    const int64_t rmin = 2 * S > 16 ? 2 * S : 16;
+    while (R > rmin && ((m + R - 1) / R) * nwin < nwave) R = (R / 2 > rmin) ? R / 2 : rmin;
+    R = R < m ? R : m;
+    const int64_t items = ((m + R - 1) / R) * nwin;
     Track dummy{0, 0};
     for (int64_t it = wave; it < items; it += nwave) {
         const int64_t b = it / nwin, wdx = it - b * nwin;
@@ -189,15 +202,19 @@ __global__ void k_write_result(ms_square *out, mshost::ScratchHeader *hdr, int64
 
 // ---------------------------------------------------------------------------------- batched
 struct BatchCounters {
-    unsigned long long head;    // next work item
-    unsigned long long total;   // total tiles
-    uint32_t sat_count;
-    uint32_t done;
-    uint32_t overflow;
-    uint32_t pad;
+    uint32_t error;   // bit 1: the device prefix disagrees with the host's tile count
+    uint32_t pad[7];
 };
 
-// One block: clear per-matrix keys and flags, tile-count prefix (exclusive), counters.
+// One block: clear per-matrix keys and flags, exclusive prefix of tile counts.
+template <class TS>
+__device__ __forceinline__ uint64_t tiles_in(const ms_matrix &d) {
+    if (d.m <= 0 || d.n <= 0) return 0;
+    const int64_t nwords = (d.n + 63) >> 6;
+    return (uint64_t)(((d.m + TS::TR - 1) / TS::TR) *
+                      ((nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS));
+}
+
 template <class TS>
 __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict__ mats,
                                                      int64_t count,
@@ -213,18 +230,12 @@ __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict
     for (int64_t i = lo; i < hi; ++i) {
         keys[i] = 0;
         flags[i] = 0;
-        const ms_matrix d = mats[i];
-        const int64_t nwords = (d.n + 63) >> 6;
-        const int64_t nt = (d.m > 0 && d.n > 0)
-                               ? ((d.m + TS::TR - 1) / TS::TR) *
-                                     ((nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS)
-                               : 0;
-        s += (uint64_t)nt;
+        s += tiles_in<TS>(mats[i]);
     }
     part[tid] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        uint64_t v = tid >= off ? part[tid - off] : 0;
+        const uint64_t v = tid >= off ? part[tid - off] : 0;
         __syncthreads();
         part[tid] += v;
         __syncthreads();
@@ -232,21 +243,11 @@ __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict
     uint64_t run = part[tid] - s;  // exclusive start of this thread's range
     for (int64_t i = lo; i < hi; ++i) {
         prefix[i] = run;
-        const ms_matrix d = mats[i];
-        const int64_t nwords = (d.n + 63) >> 6;
-        const int64_t nt = (d.m > 0 && d.n > 0)
-                               ? ((d.m + TS::TR - 1) / TS::TR) *
-                                     ((nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS)
-                               : 0;
-        run += (uint64_t)nt;
+        run += tiles_in<TS>(mats[i]);
     }
     if (tid == 1023) {
         prefix[count] = part[1023];
-        ctr->head = 0;
-        ctr->total = part[1023];
-        ctr->sat_count = 0;
-        ctr->done = 0;
-        ctr->overflow = 0;
+        ctr->error = 0;
     }
 }
 
@@ -269,12 +270,13 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
                                                        int64_t count,
                                                        unsigned long long *__restrict__ keys,
                                                        const uint64_t *__restrict__ prefix,
-                                                       BatchCounters *ctr,
-                                                       uint64_t *__restrict__ sat_list,
-                                                       uint64_t sat_cap, uint64_t total) {
-    const int lane = __lane_id();
+                                                       uint32_t *__restrict__ flags,
+                                                       BatchCounters *ctr, uint64_t total) {
+    __shared__ uint64_t lx[4][LDS_WORDS];
+    __shared__ int32_t lc[4][LDS_WORDS];
+    const int wib = threadIdx.x / WAVE;
     if (__hip_atomic_load(prefix + count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != total) {
-        if (lane == 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->overflow, 2u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->error, 2u);
         return;
     }
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -286,51 +288,13 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
         const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
         const int64_t t = (int64_t)(item - prefix[mi]);
         const int64_t ty = t / ntx, tx = t - ty * ntx;
-        TileSink sink{keys + mi, &ctr->sat_count, sat_list, sat_cap, (uint64_t)mi << 40};
-        tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, t, sink);
+        const TileSink sink{keys + mi, flags + mi, WaveLds{lx[wib], lc[wib]}};
+        tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, sink);
     }
 }
 
-__global__ __launch_bounds__(64) void k_exact_batched(const ms_matrix *__restrict__ mats,
-                                                      unsigned long long *__restrict__ keys,
-                                                      uint32_t *__restrict__ flags,
-                                                      BatchCounters *ctr,
-                                                      const uint64_t *__restrict__ sat_list,
-                                                      uint64_t sat_cap, int64_t tile_rows,
-                                                      int64_t kc) {
-    __shared__ uint64_t lx[LDS_WORDS];
-    __shared__ int32_t lc[LDS_WORDS];
-    const WaveLds lds{lx, lc};
-    const int lane = __lane_id();
-    const uint32_t cnt = load_relaxed_u32(&ctr->sat_count);
-    if (load_relaxed_u32(&ctr->overflow) & 2u) return;
-    if ((uint64_t)cnt > sat_cap) {
-        if (lane == 0 && blockIdx.x == 0) atomicOr(&ctr->overflow, 1u);
-        return;
-    }
-    for (int64_t s = blockIdx.x; s < (int64_t)cnt; s += gridDim.x) {
-        const uint64_t e = sat_list[s];
-        const int64_t mi = (int64_t)(e >> 40);
-        const int64_t tid = (int64_t)(e & 0xFFFFFFFFFFull);
-        const ms_matrix d = mats[mi];
-        const int64_t nwords = (d.n + 63) >> 6;
-        const int64_t ntx = (nwords + mshost::PROBE_TILE_WORDS - 1) / mshost::PROBE_TILE_WORDS;
-        const int64_t ty = tid / ntx, tx = tid - ty * ntx;
-        const int64_t ra = ty * tile_rows, rb = ra + tile_rows < d.m ? ra + tile_rows : d.m;
-        const int64_t xa = tx * mshost::PROBE_TILE_WORDS * 64;
-        const int64_t xe = xa + mshost::PROBE_TILE_WORDS * 64;
-        const int64_t xb = xe < d.n ? xe : d.n;
-        Track t{0, INT64_MAX};
-        if (exact_region<EX_NG, EX_CPL>(d.bits, d.m, d.n, d.ld_words, ra, rb, xa, xb, kc, t, lds)) {
-            if (lane == 0 && t.v > 0) atomicMax(keys + mi, make_key(t.v, t.pos));
-        } else if (lane == 0) {
-            atomicOr(flags + mi, 1u);
-        }
-    }
-}
-
-// Key -> result per matrix; matrices whose saturated tiles needed a halo wider than the exact
-// pass supports are finished by block 0 with the serial pass (it owns the state buffer).
+// Key -> result per matrix; matrices with a square too wide for the windowed pass are finished
+// by block 0 with the serial pass (it owns the state buffer).
 __global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict__ mats,
                                                     int64_t count,
                                                     const unsigned long long *__restrict__ keys,
@@ -338,22 +302,20 @@ __global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict_
                                                     const BatchCounters *ctr,
                                                     int32_t *serial_state, ms_square *out) {
     const int lane = __lane_id();
-    const uint32_t ovf = load_relaxed_u32(&ctr->overflow);
-    if (ovf & 2u) {  // inconsistent batch: report every result as failed
+    if (load_relaxed_u32(&ctr->error) & 2u) {  // inconsistent batch: report every result failed
         for (int64_t i = blockIdx.x; i < count; i += gridDim.x)
             if (lane == 0) out[i] = ms_square{-1, -1, -1};
         return;
     }
-    const bool overflow = ovf != 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         const ms_matrix d = mats[i];
-        const bool serial = d.m > 0 && d.n > 0 && (load_relaxed_u32(flags + i) || overflow);
+        const bool serial = d.m > 0 && d.n > 0 && load_relaxed_u32(flags + i);
         if (!serial && lane == 0) write_result(load_relaxed(keys + i), d.n, out + i);
     }
     if (blockIdx.x != 0) return;
     for (int64_t i = 0; i < count; ++i) {
         const ms_matrix d = mats[i];
-        if (!(d.m > 0 && d.n > 0 && (load_relaxed_u32(flags + i) || overflow))) continue;
+        if (!(d.m > 0 && d.n > 0 && load_relaxed_u32(flags + i))) continue;
         const int64_t nw64 = ((d.n + 63) >> 6) * 64;
         Track tr{0, INT64_MAX};
         serial_dp<false>(d.bits, d.m, d.n, d.ld_words, nullptr, 0, serial_state,
@@ -387,47 +349,42 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int64_t n,
                           int64_t ldb, uint64_t *bits, int64_t ldw) {
-    const int64_t groups = 4 * cdiv(n, 64);
-    dim3 block(256);
-    dim3 grid((unsigned)std::min<int64_t>(cdiv(groups, 256), 1 << 20),
-              (unsigned)std::min<int64_t>(m, 65535));
-    const int aligned = ((uintptr_t)a % 16 == 0) && (ldb % 16 == 0);
-    hipLaunchKernelGGL(msk::k_pack_u8, grid, block, 0, env.stream, a, m, n, ldb, bits, ldw,
-                       aligned);
+    const int64_t words = m * cdiv(n, 64);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(words, 256),
+                                                                   (int64_t)env.num_cus * 32));
+    const uintptr_t al = (uintptr_t)a | (uintptr_t)ldb;
+    const dim3 g((unsigned)blocks), b(256);
+    if (al % 16 == 0) hipLaunchKernelGGL(msk::k_pack_u8<16>, g, b, 0, env.stream, a, m, n, ldb, bits, ldw);
+    else if (al % 8 == 0) hipLaunchKernelGGL(msk::k_pack_u8<8>, g, b, 0, env.stream, a, m, n, ldb, bits, ldw);
+    else if (al % 4 == 0) hipLaunchKernelGGL(msk::k_pack_u8<4>, g, b, 0, env.stream, a, m, n, ldb, bits, ldw);
+    else hipLaunchKernelGGL(msk::k_pack_u8<1>, g, b, 0, env.stream, a, m, n, ldb, bits, ldw);
     return hipGetLastError();
 }
 
 template <class TS>
-static void launch_probe(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
-                         int64_t ldw, ScratchHeader *hdr, uint64_t *sat_list, uint64_t sat_cap,
-                         int64_t *ntx_out) {
-    const int64_t nwords = cdiv(n, 64);
-    const int64_t ntx = cdiv(nwords, TS::OWN_WORDS);
+static hipError_t launch_probe(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
+                               int64_t ldw, ScratchHeader *hdr) {
+    const int64_t ntx = cdiv(cdiv(n, 64), TS::OWN_WORDS);
     const int64_t ntiles = cdiv(m, TS::TR) * ntx;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 4),
                                                                    (int64_t)env.num_cus * 8));
-    msk::TileSink sink{&hdr->key, &hdr->sat_count, sat_list, sat_cap, 0};
     hipLaunchKernelGGL(msk::k_probe<TS>, dim3((unsigned)blocks), dim3(256), 0, env.stream, bits,
-                       m, n, ldw, ntiles, ntx, sink);
-    *ntx_out = ntx;
+                       m, n, ldw, ntiles, ntx, hdr);
+    return hipGetLastError();
 }
 
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
-                             int64_t n, int64_t ldw, ScratchHeader *hdr, uint64_t *sat_list,
-                             uint64_t sat_cap, int32_t *serial_state, ms_square *out) {
-    int64_t ntx = 0;
-    int kc = 16;
+                             int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
+                             ms_square *out) {
+    hipError_t e;
     switch (variant) {
-    case 0: launch_probe<TS0>(env, bits, m, n, ldw, hdr, sat_list, sat_cap, &ntx); kc = TS0::KC; break;
-    case 1: launch_probe<TS1>(env, bits, m, n, ldw, hdr, sat_list, sat_cap, &ntx); kc = TS1::KC; break;
-    default: launch_probe<TS2>(env, bits, m, n, ldw, hdr, sat_list, sat_cap, &ntx); kc = TS2::KC; break;
+    case 0: e = launch_probe<TS0>(env, bits, m, n, ldw, hdr); break;
+    case 1: e = launch_probe<TS1>(env, bits, m, n, ldw, hdr); break;
+    default: e = launch_probe<TS2>(env, bits, m, n, ldw, hdr); break;
     }
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t blocks = (int64_t)env.num_cus * 4;
-    hipLaunchKernelGGL(msk::k_exact, dim3((unsigned)blocks), dim3(64), 0, env.stream, bits, m, n,
-                       ldw, hdr, sat_list, (int64_t)sat_cap, ntx, probe_tile_rows(variant),
-                       (int64_t)kc, serial_state, out);
+    hipLaunchKernelGGL(msk::k_finalize, dim3(1), dim3(64), 0, env.stream, bits, m, n, ldw, hdr,
+                       serial_state, out);
     return hipGetLastError();
 }
 
@@ -435,7 +392,7 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
                              int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state) {
     const int vec_ok = ((uintptr_t)dp % 16 == 0) && (ld_dp % 4 == 0);
-    const int64_t items_bound = cdiv(m, band_rows) * cdiv(n, 64);
+    const int64_t items_bound = cdiv(m, 16) * cdiv(n, 64);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(items_bound, 4),
                                                                    (int64_t)env.num_cus * 8));
     if (map_cols == 8) {
@@ -479,7 +436,6 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
         }
         maxw = std::max<int64_t>(maxw, cdiv(std::max<int64_t>(h_mats[i].n, 1), 64));
     }
-    L.sat_cap = tiles;
     L.total_tiles = tiles;
     L.max_nwords = maxw;
     size_t off = 0;
@@ -487,7 +443,6 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
     L.keys = off; off = align256(off + sizeof(unsigned long long) * (size_t)count);
     L.prefix = off; off = align256(off + sizeof(uint64_t) * (size_t)(count + 1));
     L.flags = off; off = align256(off + sizeof(uint32_t) * (size_t)count);
-    L.sat_list = off; off = align256(off + sizeof(uint64_t) * (size_t)std::max<uint64_t>(tiles, 1));
     L.serial_state = off; off = align256(off + sizeof(int32_t) * 2 * 64 * (size_t)maxw);
     L.total = off;
     return L;
@@ -500,7 +455,6 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     auto *keys = reinterpret_cast<unsigned long long *>(ws + L.keys);
     auto *prefix = reinterpret_cast<uint64_t *>(ws + L.prefix);
     auto *flags = reinterpret_cast<uint32_t *>(ws + L.flags);
-    auto *sat = reinterpret_cast<uint64_t *>(ws + L.sat_list);
     auto *state = reinterpret_cast<int32_t *>(ws + L.serial_state);
     hipLaunchKernelGGL(msk::k_batch_init<TS>, dim3(1), dim3(1024), 0, env.stream, mats, count,
                        keys, prefix, flags, ctr);
@@ -509,12 +463,8 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     const int64_t pblocks = std::max<int64_t>(
         1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 4), (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)pblocks), dim3(256), 0,
-                       env.stream, mats, count, keys, prefix, ctr, sat, L.sat_cap,
+                       env.stream, mats, count, keys, prefix, flags, ctr,
                        (uint64_t)L.total_tiles);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(msk::k_exact_batched, dim3((unsigned)(env.num_cus * 4)), dim3(64), 0,
-                       env.stream, mats, keys, flags, ctr, sat, L.sat_cap, (int64_t)TS::TR,
-                       (int64_t)TS::KC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t fb = std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)env.num_cus * 4));
     hipLaunchKernelGGL(msk::k_batch_final, dim3((unsigned)fb), dim3(64), 0, env.stream, mats,

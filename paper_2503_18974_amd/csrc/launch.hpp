@@ -9,16 +9,14 @@
 
 namespace mshost {
 
-// Device scratch of a context (single-matrix calls).  All counters return to zero at the end
-// of every call, so the scratch needs clearing only once, when it is allocated.
+// Device scratch of a context (single-matrix calls).  The key and flag return to zero at the
+// end of every call, so the scratch needs clearing only once, when it is allocated.
 struct ScratchHeader {
     unsigned long long key;     // running best (side, position) key
-    uint32_t sat_count;         // saturated tiles queued by the erosion pass
-    uint32_t done;              // waves finished in the exact pass
-    uint32_t serial_flag;       // a saturated tile needs the serial pass
+    uint32_t serial_flag;       // a square was too wide for the windowed exact pass
     uint32_t pad0;
     ms_square result;           // last result (read by the map pass)
-    uint64_t pad1[2];
+    uint64_t pad1[3];
 };
 static_assert(sizeof(ScratchHeader) == 64, "header layout");
 
@@ -43,8 +41,8 @@ hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int
 
 // Largest square of one matrix; result into hdr->result and, if non-null, *out.
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
-                             int64_t n, int64_t ldw, ScratchHeader *hdr, uint64_t *sat_list,
-                             uint64_t sat_cap, int32_t *serial_state, ms_square *out);
+                             int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
+                             ms_square *out);
 
 // dp map of one matrix; reads S from *maxsq on the device (a largest-square result).
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
@@ -57,8 +55,7 @@ hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHead
 
 // Batched: workspace layout and launches.
 struct BatchLayout {
-    size_t keys, prefix, counters, sat_list, serial_state, flags, total;
-    uint64_t sat_cap;
+    size_t keys, prefix, counters, serial_state, flags, total;
     uint64_t total_tiles;
     int64_t max_nwords;
 };

@@ -74,3 +74,24 @@ def test_batched_repeat_reuses_workspace(dev):
         b.run()
         got = b.results()
         assert [(g.side, g.row, g.col) for g in got] == refs
+
+
+def test_batched_graph_replays(dev, monkeypatch):
+    """The launch sequence recorded once into a HIP graph: every replay (with eager work and
+    synchronisation between replays) gives the oracle's results."""
+    import torch
+    announce("batched graph")
+    monkeypatch.setenv("MAXSQ_GRAPH", "1")
+    mats = make_mix(5, 16)
+    items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
+    b = M.Batch(items)
+    refs = [oracle.max_square(a) for a in mats]
+    for k in range(4):
+        b.out.fill_(-5)
+        b.run()
+        torch.cuda.synchronize()
+        got = b.results()
+        assert [(g.side, g.row, g.col) for g in got] == refs, "replay %d" % k
+        d, n = items[k]
+        single = M.max_square(d, n)       # eager work between replays
+        assert (single.side, single.row, single.col) == refs[k]
