@@ -75,6 +75,22 @@ __device__ __forceinline__ int32_t leading_ones(uint64_t v) {
     return (v == ~0ull) ? 64 : (int32_t)__clzll(~v);
 }
 
+// A value every lane of the wave holds equally, moved to a scalar register so the compiler
+// treats what depends on it (loop bounds, branches, addresses) as wave-uniform.
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int32_t uniform(int32_t v) {
+    return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+// Global index of the calling wave (uniform).
+__device__ __forceinline__ int64_t wave_index() {
+    return uniform((int64_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE));
+}
+
 // Lane l receives lane l-1's value, lane 0 receives `first` (DPP wave_shr:1).
 __device__ __forceinline__ int32_t from_left_lane(int32_t v, int32_t first) {
     return __builtin_amdgcn_update_dpp(first, v, 0x138, 0xf, 0xf, false);
@@ -116,8 +132,9 @@ __device__ __forceinline__ Track wave_track(Track t) {
 constexpr int LDS_WORDS = 1024;  // staged packed words per wave
 
 struct WaveLds {
-    uint64_t *x;   // LDS_WORDS packed words
-    int32_t *c;    // LDS_WORDS entering row runs
+    uint64_t *x;   // `cap` packed words
+    int32_t *c;    // `cap` entering row runs
+    int cap = LDS_WORDS;
 };
 
 template <int NGMAX, int CPL, bool STORE, bool TRACK>
@@ -127,6 +144,16 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                       WaveLds lds) {
     static_assert(CPL == 4 || CPL == 8, "columns per lane");
     static_assert(NGMAX * CPL <= 64, "window words must fit one wave");
+    rh = uniform(rh);
+    ra = uniform(ra);
+    rb = uniform(rb);
+    xh = uniform(xh);
+    xa = uniform(xa);
+    xb = uniform(xb);
+    ng = uniform(ng);
+    ldw = uniform(ldw);
+    n = uniform(n);
+    ld_dp = uniform(ld_dp);
     constexpr int GW = 64 * CPL;  // columns per group
     constexpr int LPW = 64 / CPL; // lanes per word
     const int lane = __lane_id();
@@ -135,11 +162,12 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
     const int nww = ng * CPL;                    // window words
-    const int rc_max = LDS_WORDS / nww;          // rows per chunk
+    const int rc_max = lds.cap / nww;            // rows per chunk
     const int fl_w = lane % nww, fl_r = lane / nww, fl_rpp = 64 / nww;
     const int64_t fl_word = (xh >> 6) + fl_w;
     const bool fl_ok = fl_r < fl_rpp && fl_word < nwords;
     const uint64_t fl_mask = (fl_word == nwords - 1) ? lastmask : ~0ull;
+    const int64_t fl_wc = fl_word < nwords ? fl_word : nwords - 1;  // always a valid word
 
     int32_t H[NGMAX][CPL], D[NGMAX][CPL];
 #pragma unroll
@@ -152,11 +180,22 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
 
     for (int64_t r0 = rh; r0 < rb; r0 += rc_max) {
         const int rc = (int)(rb - r0 < rc_max ? rb - r0 : rc_max);
-        // stage the chunk's words
-        for (int r = fl_r; r < rc; r += fl_rpp) {
-            uint64_t v = 0;
-            if (fl_ok) v = bits[(r0 + r) * ldw + fl_word] & fl_mask;
-            if (fl_r < fl_rpp) lds.x[r * nww + fl_w] = v;
+        // stage the chunk's words: eight rows' loads in flight per batch, from in-bounds
+        // (clamped) addresses, masked afterwards
+        constexpr int FB = 8;
+        for (int rb0 = fl_r; rb0 < rc; rb0 += FB * fl_rpp) {
+            uint64_t v[FB];
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int r = rb0 + u * fl_rpp;
+                const int r_c = r < rc ? r : rc - 1;
+                v[u] = bits[(r0 + r_c) * ldw + fl_wc];
+            }
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int r = rb0 + u * fl_rpp;
+                if (r < rc && fl_r < fl_rpp) lds.x[r * nww + fl_w] = fl_ok ? (v[u] & fl_mask) : 0ull;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // row run entering each word (zero at the window's left edge)
@@ -272,6 +311,9 @@ __device__ void serial_dp(const uint64_t *__restrict__ bits, int64_t m, int64_t 
                           int32_t *__restrict__ dp, int64_t ld_dp, int32_t *__restrict__ stH,
                           int32_t *__restrict__ stD, Track &tr) {
     const int lane = __lane_id();
+    m = uniform(m);
+    n = uniform(n);
+    ldw = uniform(ldw);
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
     for (int64_t c = lane; c < nwords * 64; c += WAVE) {
@@ -288,11 +330,12 @@ __device__ void serial_dp(const uint64_t *__restrict__ bits, int64_t m, int64_t 
             uint64_t v[UNROLL];
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                const int64_t k = k0 + u;
-                v[u] = row_word(row, k, nwords, lastmask);
+                const int64_t k = k0 + u < nwords ? k0 + u : nwords - 1;  // clamped: loads batch
+                const uint64_t raw = row[k];
+                v[u] = (k0 + u < nwords) ? ((k == nwords - 1) ? (raw & lastmask) : raw) : 0ull;
                 const int64_t c = k * 64 + lane;
-                h0[u] = (k < nwords) ? stH[c] : 0;
-                d0[u] = (k < nwords) ? stD[c] : 0;
+                h0[u] = stH[c];
+                d0[u] = stD[c];
             }
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
@@ -446,6 +489,11 @@ template <class TS>
 __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int64_t ty, int64_t tx, const TileSink &sink) {
     constexpr int RPL = TS::RPL;
+    m = uniform(m);
+    n = uniform(n);
+    ldw = uniform(ldw);
+    ty = uniform(ty);
+    tx = uniform(tx);
     const int lane = __lane_id();
     const int wl = lane & 15, rg = lane >> 4;
     const int64_t nwords = (n + 63) >> 6;
@@ -454,10 +502,19 @@ __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_
     const bool wvalid = wlane >= 0 && wlane < nwords;
     const uint64_t wmask = (wlane == nwords - 1) ? last_word_mask(n) : ~0ull;
     uint64_t E[RPL], T[RPL];
+    // all loads from clamped (in-bounds) addresses first, so they are in flight together; the
+    // rows and words outside the matrix are zeroed afterwards
+    const int64_t wl_c = wlane < 0 ? 0 : (wlane < nwords ? wlane : nwords - 1);
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int64_t row = tile_r0 + rg * RPL + r;
-        E[r] = (wvalid && row >= 0 && row < m) ? (bits[row * ldw + wlane] & wmask) : 0ull;
+        const int64_t row_c = row < 0 ? 0 : (row < m ? row : m - 1);
+        E[r] = bits[row_c * ldw + wl_c];
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int64_t row = tile_r0 + rg * RPL + r;
+        E[r] = (wvalid && row >= 0 && row < m) ? (E[r] & wmask) : 0ull;
     }
     const bool lane_ok = wl != 0 && wvalid;
     // best side found so far by any tile (read now so the load overlaps the erosion steps)

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits
     __shared__ int32_t lc[4][LDS_WORDS];
     const int wib = threadIdx.x / WAVE;
     const TileSink sink{&hdr->key, &hdr->serial_flag, WaveLds{lx[wib], lc[wib]}};
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     for (int64_t t = wave; t < ntiles; t += nwave) {
         const int64_t ty = t / ntx, tx = t - ty * ntx;
@@ -125,15 +125,15 @@ __global__ __launch_bounds__(64) void k_finalize(const uint64_t *__restrict__ bi
                                                  mshost::ScratchHeader *hdr,
                                                  int32_t *serial_state, ms_square *out) {
     const int lane = __lane_id();
-    unsigned long long key;
-    if (load_relaxed_u32(&hdr->serial_flag)) {
+    // both loads in flight together (device-scope: written by other waves' atomics)
+    unsigned long long key = load_relaxed(&hdr->key);
+    const uint32_t flag = load_relaxed_u32(&hdr->serial_flag);
+    if (flag) {
         const int64_t nw64 = ((n + 63) >> 6) * 64;
         Track tr{0, INT64_MAX};
         serial_dp<false>(bits, m, n, ldw, nullptr, 0, serial_state, serial_state + nw64, tr);
         const Track w = wave_track(tr);
         key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
-    } else {
-        key = load_relaxed(&hdr->key);
     }
     if (lane == 0) {
         write_result(key, n, &hdr->result);
@@ -144,6 +144,9 @@ __global__ __launch_bounds__(64) void k_finalize(const uint64_t *__restrict__ bi
 }
 
 // ---------------------------------------------------------------------------------- map
+// One instantiation per window width: a kernel acts only when s_lo < S <= its window's reach
+// (and, when `serial_beyond`, runs the serial sweep for any larger S), so a narrow, lean kernel
+// serves the common small squares and a wide one the rest; the other exits at once.
 // Band height: at least band_rows and 4 S (so the S-row head start costs at most a quarter),
 // halved while that leaves fewer items than waves, down to 2 S (or 16 rows).
 template <int NGMAX, int CPL>
@@ -152,17 +155,20 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
                                                int64_t ld_dp,
                                                const ms_square *__restrict__ maxsq,
                                                int64_t band_rows, int32_t *serial_state,
-                                               int vec_ok) {
+                                               int vec_ok, int64_t s_lo, int serial_beyond) {
     constexpr int64_t GW = 64 * CPL;
     constexpr int64_t WIN = NGMAX * GW;
-    __shared__ uint64_t lx[4][LDS_WORDS];
-    __shared__ int32_t lc[4][LDS_WORDS];
-    const WaveLds lds{lx[threadIdx.x / WAVE], lc[threadIdx.x / WAVE]};
-    const int64_t S = __hip_atomic_load(&maxsq->side, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    constexpr int64_t REACH = WIN - 64;   // largest S whose halo leaves a 64-column output
+    constexpr int LDSW = NGMAX * CPL <= 8 ? LDS_WORDS / 2 : LDS_WORDS;
+    __shared__ uint64_t lx[4][LDSW];
+    __shared__ int32_t lc[4][LDSW];
+    const WaveLds lds{lx[threadIdx.x / WAVE], lc[threadIdx.x / WAVE], LDSW};
+    const int64_t S = uniform(maxsq->side);
+    if (S <= s_lo) return;
     const int64_t hc = (S + 63) & ~(int64_t)63;
-    if (hc + 64 > WIN) {
-        // too large for a register window: one wave sweeps the whole matrix
-        if (blockIdx.x == 0 && threadIdx.x < WAVE) {
+    if (hc > REACH) {
+        // too large for this window: one wave sweeps the whole matrix (widest kernel only)
+        if (serial_beyond && blockIdx.x == 0 && threadIdx.x < WAVE) {
             const int64_t nw64 = ((n + 63) >> 6) * 64;
             Track tr{0, INT64_MAX};
             serial_dp<true>(bits, m, n, ldw, dp, ld_dp, serial_state, serial_state + nw64, tr);
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
     ng = ng < 1 ? 1 : (ng > NGMAX ? NGMAX : ng);
     const int64_t ow = ng * GW - hc;
     const int64_t nwin = (n + ow - 1) / ow;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     int64_t R = band_rows > 4 * S ? band_rows : 4 * S;
     const int64_t rmin = 2 * S > 16 ? 2 * S : 16;
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->error, 2u);
         return;
     }
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t wave = (uint64_t)wave_index();
     const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
     for (uint64_t item = wave; item < total; item += nwave) {
         const int64_t mi = find_matrix(prefix, count, item);
@@ -395,16 +401,27 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
     const int64_t items_bound = cdiv(m, 16) * cdiv(n, 64);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(items_bound, 4),
                                                                    (int64_t)env.num_cus * 8));
+    const dim3 g((unsigned)blocks), b(256);
+    // narrow kernel: squares up to 448 (8 x 64 - 64); window 512 columns, 1 or 2 groups
+    constexpr int64_t NARROW_REACH = 448;
     if (map_cols == 8) {
-        hipLaunchKernelGGL((msk::k_dpmap<4, 8>), dim3((unsigned)blocks), dim3(256), 0, env.stream,
-                           bits, m, n, ldw, dp, ld_dp, maxsq, (int64_t)band_rows, serial_state,
-                           vec_ok);
+        hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0);
     } else {
-        hipLaunchKernelGGL((msk::k_dpmap<8, 4>), dim3((unsigned)blocks), dim3(256), 0, env.stream,
-                           bits, m, n, ldw, dp, ld_dp, maxsq, (int64_t)band_rows, serial_state,
-                           vec_ok);
+        hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // a square wider than the narrow kernel's reach can only exist when both sides exceed it
+    if (std::min(m, n) > NARROW_REACH) {
+        // one block per CU: cheap to retire when idle, and wide squares make few, long items
+        const dim3 gw((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, env.num_cus)));
+        hipLaunchKernelGGL((msk::k_dpmap<8, 4>), gw, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, NARROW_REACH, 1);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,
