@@ -9,10 +9,13 @@ and the int32 dp map (ms_square_map_from_max).  value = total cells per second o
 timed steps.
 
 Also reported: the dp-map kernel's achieved algorithmic bandwidth (HIP events around every
-map launch inside the timed steps) against the 8 TB/s HBM peak, the batched entry point over
-the same 45 packed matrices next to the per-matrix loop, and the CPU oracle timed on the host.
+map launch inside the timed steps) against the 8 TB/s HBM peak; the batched entry point over
+the same 45 packed matrices next to the per-matrix loop; the three large single matrices
+(32768^2 p=0.9, 4096 x 262144 with a planted 1500^2 block, 16384^2 blob) with the caches
+flushed before every timed call; the 10000-matrix batched workload against the plain
+per-matrix loop; and the CPU oracle (plus the paper's Algorithm 1 in C) timed on the host.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-large] [--no-c4]
 """
 import argparse
 import json
@@ -26,6 +29,52 @@ sys.path.insert(0, ROOT)
 METRIC = "Gcells/s plain vs batched, % of HBM roofline; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 MAP_BYTES_PER_CELL = 4.0 + 0.125   # int32 map written once + packed input read once
+PROBE_BYTES_PER_CELL = 0.125       # packed input read once
+FLUSH_BYTES = 1 << 30              # > 256 MB last-level cache + 8 x 4 MB L2
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_dpmap_paper_grid_traffic.md")
+KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp")
+
+
+def kernel_fingerprint():
+    """sha256 (first 16 hex digits) of the kernel sources: a stored counter measurement is only
+    reported while the kernels it was taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_18974_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per dp-map launch from the committed counter summary, or None when there is
+    none or the kernels changed since it was taken."""
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fp = re.search(r"^source_fingerprint:\s*([0-9a-f]+)", text, re.M)
+    tb = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not fp or not tb or fp.group(1) != kernel_fingerprint():
+        return None
+    return float(tb.group(1))
+
+
+def copy_calibration():
+    """A plain 256 MiB device-to-device copy, three times: what FETCH_SIZE / WRITE_SIZE read for
+    a kernel of known traffic (the calibration of the counter figures)."""
+    import torch
+    n = 256 << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
 def log(*a):
@@ -49,6 +98,231 @@ def cpu_baseline(mats, budget_s):
                       "each, %.1f s" % (len(names), ", ".join(names[:3]), done_cells / 1e6, t_total)}
 
 
+def cpu_freq_baseline(mats, budget_s):
+    """The paper's Algorithm 1 (plain C, largest side only) next to the oracle's rolling-row dp
+    on the same matrices: the host's DP/frequency ratio, for context."""
+    import oracle
+    t_f = t_d = 0.0
+    done = 0
+    for (n, d, p, seed), a in mats:
+        t0 = time.perf_counter()
+        oracle.freq_alg1(a)
+        t1 = time.perf_counter()
+        oracle.max_square(a)
+        t2 = time.perf_counter()
+        t_f += t1 - t0
+        t_d += t2 - t1
+        done += 1
+        if t_f + t_d > budget_s:
+            break
+    cells = sum(a.size for _, a in mats[:done])
+    return {"freq_alg1_gcells_s": cells / t_f / 1e9, "dp_rolling_gcells_s": cells / t_d / 1e9,
+            "dp_over_freq_time": t_d / t_f, "cores": 1,
+            "sample": "%d grid matrices, %.0f Mcells, largest side only" % (done, cells / 1e6)}
+
+
+def large_section(L, h, dev, names, reps, golden):
+    """Each large matrix packed in HBM: ms_max_square, then ms_square_map_from_max, each timed
+    alone with HIP events after a 1 GiB write that evicts the caches."""
+    import numpy as np
+    import torch
+    import workloads as W
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    flush = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device=dev)
+    out = {}
+    for name in names:
+        g = golden[name]
+        log("large %s: generating" % name)
+        bits, m, n, _ = W.large_packed(name)
+        import hashlib
+        if hashlib.sha256(bits.tobytes()).hexdigest() != g["sha256_packed"]:
+            raise SystemExit("%s: regenerated input differs from the recorded one" % name)
+        d = torch.from_numpy(bits.view(np.int64)).to(dev)
+        del bits
+        dp = torch.empty((m, n), dtype=torch.int32, device=dev)
+        res = torch.zeros(3, dtype=torch.int64, device=dev)
+        ldw = d.stride(0)
+        for _ in range(2):
+            if L.ms_max_square(h, d.data_ptr(), m, n, ldw, res.data_ptr(), sp):
+                raise RuntimeError("ms_max_square failed")
+            if L.ms_square_map_from_max(h, d.data_ptr(), m, n, ldw, res.data_ptr(), dp.data_ptr(),
+                                        n, sp):
+                raise RuntimeError("ms_square_map_from_max failed")
+        torch.cuda.synchronize()
+        got = tuple(res.cpu().tolist())
+        if got != (g["side"], g["row"], g["col"]):
+            raise SystemExit("%s: result %s differs from the oracle's %s"
+                             % (name, got, (g["side"], g["row"], g["col"])))
+        if int(dp.max().item()) != g["side"]:
+            raise SystemExit("%s: dp map maximum differs from the side" % name)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+        for r in range(reps):
+            flush.fill_(r & 0xff)
+            ev[r][0].record(stream)
+            L.ms_max_square(h, d.data_ptr(), m, n, ldw, res.data_ptr(), sp)
+            ev[r][1].record(stream)
+            flush.fill_((r + 1) & 0xff)
+            ev[r][2].record(stream)
+            L.ms_square_map_from_max(h, d.data_ptr(), m, n, ldw, res.data_ptr(), dp.data_ptr(), n,
+                                     sp)
+            ev[r][3].record(stream)
+        torch.cuda.synchronize()
+        t_p = sum(e[0].elapsed_time(e[1]) for e in ev) / reps * 1e-3
+        t_m = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
+        cells = m * n
+        rec = {"m": m, "n": n, "side": g["side"],
+               "max_square_us": t_p * 1e6, "max_square_gcells_s": cells / t_p / 1e9,
+               "max_square_gbs": cells * PROBE_BYTES_PER_CELL / t_p / 1e9,
+               "map_us": t_m * 1e6, "map_gcells_s": cells / t_m / 1e9,
+               "map_gbs": cells * MAP_BYTES_PER_CELL / t_m / 1e9,
+               "map_frac": cells * MAP_BYTES_PER_CELL / t_m / 1e9 / HBM_PEAK_GBS,
+               "square_map_gcells_s": cells / (t_p + t_m) / 1e9}
+        out[name] = rec
+        log("large %s %dx%d S=%d: max_square %.1f us (%.0f Gcells/s), map %.1f us (%.0f GB/s, "
+            "%.0f%% of peak)" % (name, m, n, g["side"], t_p * 1e6, rec["max_square_gcells_s"],
+                                 t_m * 1e6, rec["map_gbs"], 100 * rec["map_frac"]))
+        del d, dp
+        torch.cuda.empty_cache()
+    del flush
+    torch.cuda.empty_cache()
+    return out
+
+
+def c4_section(L, h, dev, reps):
+    """The 10000-matrix batched workload: ms_max_square_batched in one launch sequence against
+    the plain loop of ms_max_square calls, both checked against the oracle's stored results."""
+    import hashlib
+    import numpy as np
+    import torch
+    import paper_2503_18974_amd as M
+    import workloads as W
+    path = os.path.join(ROOT, "tests", "golden", "c4_results.txt")
+    lines = open(path).read().splitlines()
+    want_sha = lines[1].split()[-1]
+    ref = np.array([[int(x) for x in ln.split()] for ln in lines if not ln.startswith("#")])
+    count = len(ref)
+    log("c4: generating %d matrices" % count)
+    mats, m, n, p = W.batch_packed(count)
+    hs = hashlib.sha256()
+    for a in mats:
+        hs.update(a.tobytes())
+    if hs.hexdigest() != want_sha:
+        raise SystemExit("c4: regenerated inputs differ from the recorded ones")
+    sizes = [a.size for a in mats]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    flat = np.concatenate([a.ravel() for a in mats]).view(np.int64)
+    del mats
+    big = torch.from_numpy(flat).to(dev)
+    del flat
+    items = []
+    for k in range(count):
+        w = W.words_per_row(n[k])
+        items.append((big[offs[k]:offs[k + 1]].view(int(m[k]), w), int(n[k])))
+    cells = int(np.sum(m.astype(np.int64) * n))
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    batch = M.Batch(items)
+    batch.run(stream)
+    torch.cuda.synchronize()
+    got = np.array(batch.out[:count].cpu().tolist())
+    if not np.array_equal(got, ref[:, 3:6]):
+        bad = int(np.argmax(np.any(got != ref[:, 3:6], axis=1)))
+        raise SystemExit("c4: batched result %d %s differs from the oracle's %s"
+                         % (bad, got[bad], ref[bad, 3:6]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        batch.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1) / reps * 1e-3
+    # plain loop: one ms_max_square per matrix into its own result row
+    res = torch.zeros((count, 3), dtype=torch.int64, device=dev)
+    calls = [(t.data_ptr(), t.size(0), nn, t.size(1), res[k].data_ptr())
+             for k, (t, nn) in enumerate(items)]
+
+    def loop():
+        for pb, mm, nn, ldw, pr in calls:
+            L.ms_max_square(h, pb, mm, nn, ldw, pr, sp)
+
+    loop()
+    torch.cuda.synchronize()
+    if not np.array_equal(np.array(res.cpu().tolist()), ref[:, 3:6]):
+        raise SystemExit("c4: per-matrix results differ from the oracle")
+    t0 = time.perf_counter()
+    e0.record(stream)
+    loop_reps = max(1, reps // 5)
+    for _ in range(loop_reps):
+        loop()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = (time.perf_counter() - t0) / loop_reps
+    t_l = e0.elapsed_time(e1) / loop_reps * 1e-3
+    log("c4: batched %.3f ms (%.0f Gcells/s) vs plain loop %.1f ms (%.0f Gcells/s)"
+        % (t_b * 1e3, cells / t_b / 1e9, t_l * 1e3, cells / t_l / 1e9))
+    out = {"matrices": count, "cells": cells, "packed_bytes": int(offs[-1]) * 8,
+           "batched_ms": t_b * 1e3, "batched_gcells_s": cells / t_b / 1e9,
+           "batched_gbs": cells * PROBE_BYTES_PER_CELL / t_b / 1e9,
+           "plain_loop_ms": t_l * 1e3, "plain_loop_gcells_s": cells / t_l / 1e9,
+           "plain_loop_wall_ms": t_wall * 1e3,
+           "speedup": t_l / t_b}
+    del batch, big, items, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_section(dev, rates, count, pool_size, budget_gib):
+    """Open-loop Poisson clients at each rate against the continuous-batching server; every
+    served result is checked against the same request run alone.  The last line is the
+    one-request-at-a-time, one-launch-per-matrix server at the middle rate."""
+    from concurrent.futures import ThreadPoolExecutor
+    import torch
+    import paper_2503_18974_amd as M
+    import workloads as W
+    from paper_2503_18974_amd.serve import GpuExecutor, Server, make_requests
+    log("serve: generating a pool of %d requests" % pool_size)
+    with ThreadPoolExecutor(16) as tp:
+        pool = list(tp.map(lambda k: W.serving_request(k)[:3], range(pool_size)))
+    budget = int(budget_gib * (1 << 30))
+    ex = GpuExecutor(budget, slots=4, max_batch=512, max_n=8192)
+    pinned = [(ex.host_bits(b), m, n) for b, m, n in pool]
+    del pool
+    ref = []
+    for hb, m, n in pinned:
+        sq = M.max_square(hb.to(dev), n)
+        ref.append((sq.side, sq.row, sq.col))
+    mean_cells = sum(m * n for _, m, n in pinned) / len(pinned)
+
+    def run(executor, budget_b, rate, cnt, slots, max_batch, tag):
+        Server(executor, budget_b, slots=slots, max_batch=max_batch).run(
+            make_requests(pinned, min(cnt, 1000), rate, seed=[30003, int(rate)]))
+        reqs = make_requests(pinned, cnt, rate)
+        st = Server(executor, budget_b, slots=slots, max_batch=max_batch).run(reqs)
+        for r in reqs:
+            if r.result != ref[r.rid % len(pinned)]:
+                raise SystemExit("serve: request %d differs from the same request alone" % r.rid)
+        s = st.summary()
+        s["rate_req_s"] = rate
+        s["offered_gcells_s"] = rate * mean_cells / 1e9
+        log("serve %s %d req/s: p50 %.2f ms, p99 %.2f ms, %.1f Gcells/s, mean batch %.1f"
+            % (tag, rate, s["p50_ms"], s["p99_ms"], s["gcells_s"], s["mean_batch"]))
+        return s
+
+    out = {"pool": pool_size, "mean_cells": mean_cells, "budget_bytes": budget,
+           "map_fraction": 0.1, "requests_per_rate": count}
+    for rate in rates:
+        out["%d" % rate] = run(ex, budget, rate, count, 4, 512, "batched")
+    ex.close()
+    del ex
+    mid = rates[len(rates) // 2]
+    plain = GpuExecutor(budget, slots=1, max_batch=1, max_n=8192, plain=True)
+    out["plain_one_at_a_time_%d" % mid] = run(plain, budget, mid, max(1000, count // 4), 1, 1,
+                                               "plain")
+    plain.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,12 +332,27 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large", default="c3a,c3b,c3c")
+    ap.add_argument("--large-reps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--c4-reps", type=int, default=10)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import ctypes
     import numpy as np
@@ -74,7 +363,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     L = M.lib()
-    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_configs.json")))["c2"]
+    golden_all = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_configs.json")))
+    golden = golden_all["c2"]
 
     log("generating the 45-matrix grid")
     mats = [((n, d, p, seed), W.gen_bernoulli(n, n, p, seed)) for n, d, p, seed in W.paper_grid()]
@@ -121,15 +411,24 @@ def main():
                              % (n, n, p, tuple(res[i]), (g["side"], g["row"], g["col"])))
     log("results match the oracle on all 45 matrices; timing", args.steps, "steps")
 
+    # value: the timed steps as a caller would run them (no instrumentation between launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(None)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = cells * args.steps / elapsed / 1e9
+    # roofline: the same steps again with HIP events around every map call on its stream (an
+    # event record between launches costs a few microseconds, so it is kept out of `value`)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    instrumented_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     map_ms = sum(e0.elapsed_time(e1) for evs in ev for e0, e1 in evs)
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = cells * args.steps / elapsed / 1e9
     map_launches = len(mats) * args.steps
     map_avg_ms = map_ms / map_launches
     map_bytes_avg = MAP_BYTES_PER_CELL * cells / len(mats)
@@ -198,6 +497,15 @@ def main():
         }
         log("batched %.3f ms vs per-matrix loop %.3f ms" % (t_b, t_p))
 
+    if not args.no_large:
+        extra["large"] = large_section(L, h, dev, [x for x in args.large.split(",") if x],
+                                       args.large_reps, golden_all)
+    if not args.no_c4:
+        extra["c4_batched"] = c4_section(L, h, dev, args.c4_reps)
+    if not args.no_serve:
+        extra["serving"] = serve_section(dev, (1000, 5000, 20000), args.serve_requests,
+                                         args.serve_pool, args.serve_budget_gib)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -225,9 +533,13 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": stored_traffic(),
             "avg_launch_us": map_avg_ms * 1e3,
+            "timed_region": "%d further steps with events around every map call (%.3f ms/step)"
+                            % (args.steps, instrumented_ms),
             "bytes_per_cell": MAP_BYTES_PER_CELL,
+            "algorithmic_bytes_per_launch": map_bytes_avg,
+            "source_fingerprint": kernel_fingerprint(),
         },
     }
     if graph_value is not None:
@@ -236,6 +548,7 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(mats, args.cpu_budget)
+        out["cpu_freq_alg1"] = cpu_freq_baseline(mats, args.cpu_budget)
     ctx.close()
     print(json.dumps(out), flush=True)
 

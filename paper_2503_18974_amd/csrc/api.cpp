@@ -26,14 +26,34 @@ bool mul_overflows(int64_t a, int64_t b) {
 
 const ms_config DEFAULT_CONFIG = {1, 4, 64};
 
+// A captured batched launch sequence.  Its launch arguments (tile total, workspace layout)
+// depend on the shapes, so the entry is keyed on a hash of every (m, n, ld_words) as well as
+// on the buffers; the matrix pointers are read from the device descriptors at run time.
 struct GraphEntry {
     const void *mats;
     int64_t count;
     const void *out;
     const void *ws;
     int variant;
+    uint64_t shape_hash;
     hipGraphExec_t exec;
 };
+
+uint64_t shape_hash(const ms_matrix *h_mats, int64_t count) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the shape words
+    auto mix = [&h](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int64_t i = 0; i < count; ++i) {
+        mix((uint64_t)h_mats[i].m);
+        mix((uint64_t)h_mats[i].n);
+        mix((uint64_t)h_mats[i].ld_words);
+    }
+    return h;
+}
 
 }  // namespace
 
@@ -361,9 +381,10 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
         mshost::LaunchEnv env{c->num_cus, st};
         return hip_status(mshost::launch_batched(env, variant, d_mats, count, d_out, d_workspace, L));
     }
+    const uint64_t sh = shape_hash(h_mats, count);
     for (auto &g : c->graphs) {
         if (g.mats == d_mats && g.count == count && g.out == d_out && g.ws == d_workspace &&
-            g.variant == variant)
+            g.variant == variant && g.shape_hash == sh)
             return hip_status(hipGraphLaunch(g.exec, st));
     }
     if (!c->capture_stream) {
@@ -389,7 +410,7 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
         (void)hipGraphExecDestroy(c->graphs.front().exec);
         c->graphs.erase(c->graphs.begin());
     }
-    c->graphs.push_back(GraphEntry{d_mats, count, d_out, d_workspace, variant, exec});
+    c->graphs.push_back(GraphEntry{d_mats, count, d_out, d_workspace, variant, sh, exec});
     return hip_status(hipGraphLaunch(exec, st));
 }
 

@@ -1,0 +1,407 @@
+"""Serving loop: open-loop arrivals, admission by an HBM budget, continuous batching.
+
+Requests (a packed binary matrix, and whether the caller also wants the int32 side map)
+arrive on their own schedule.  The loop:
+
+  * queues every request whose arrival time has passed (the client never waits for the
+    server: open loop, so a server that falls behind shows up as growing latency);
+  * admits queued requests in arrival order while the device arena (the HBM budget) can hold
+    their packed bits, plus their map when one is wanted; a request that does not fit waits
+    until earlier ones complete and free their memory;
+  * launches everything admitted as one batched call on the next free stream slot
+    (ms_max_square_batched, then ms_square_map_from_max for the requests that want a map), so
+    requests that arrive while others run on the GPU join the next launch and their work
+    overlaps on the device;
+  * polls the slots' completion events, hands each result to the caller, and frees the
+    request's memory.
+
+Latency is measured from a request's arrival time to the moment the loop sees its result;
+p50/p99 come from those.  The executor is an interface so the scheduling logic is tested on
+the CPU with a simulated device (tests/test_serve.py); GpuExecutor drives the library.
+"""
+from __future__ import annotations
+
+import bisect
+import collections
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ALIGN = 256
+
+
+def _round_up(x: int, a: int = ALIGN) -> int:
+    return (int(x) + a - 1) // a * a
+
+
+@dataclass
+class Request:
+    """One detection request.  `bits` is the packed matrix on the host (uint64 or int64,
+    (m, ld_words)); `arrival` is seconds after the start of the run."""
+    rid: int
+    m: int
+    n: int
+    bits: object
+    arrival: float
+    want_map: bool = False
+    # filled in by the server
+    admitted: float | None = None
+    launched: float | None = None
+    done: float | None = None
+    result: tuple | None = None
+    error: str | None = None
+
+    @property
+    def cells(self) -> int:
+        return int(self.m) * int(self.n)
+
+    @property
+    def ld_words(self) -> int:
+        return max(1, (int(self.n) + 63) // 64)
+
+    @property
+    def bits_bytes(self) -> int:
+        return _round_up(int(self.m) * self.ld_words * 8)
+
+    @property
+    def map_bytes(self) -> int:
+        return _round_up(int(self.m) * int(self.n) * 4) if self.want_map else 0
+
+    @property
+    def device_bytes(self) -> int:
+        return self.bits_bytes + self.map_bytes
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.done is None else self.done - self.arrival
+
+
+class Arena:
+    """First-fit allocator over [0, capacity) in ALIGN-byte units, with coalescing on free.
+    Offsets only: the executor maps them onto one device buffer."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity) // ALIGN * ALIGN
+        self.free_starts = [0]              # sorted
+        self.free_len = {0: self.capacity}
+        self.used = {}
+        self.in_use = 0
+        self.peak = 0
+
+    def alloc(self, nbytes: int):
+        size = _round_up(max(int(nbytes), 1))
+        for i, s in enumerate(self.free_starts):
+            ln = self.free_len[s]
+            if ln >= size:
+                del self.free_len[s]
+                self.free_starts.pop(i)
+                if ln > size:
+                    rest = s + size
+                    self.free_len[rest] = ln - size
+                    bisect.insort(self.free_starts, rest)
+                self.used[s] = size
+                self.in_use += size
+                self.peak = max(self.peak, self.in_use)
+                return s
+        return None
+
+    def free(self, off: int) -> None:
+        size = self.used.pop(off)
+        self.in_use -= size
+        i = bisect.bisect_left(self.free_starts, off)
+        # merge with the following block
+        if i < len(self.free_starts) and self.free_starts[i] == off + size:
+            nxt = self.free_starts.pop(i)
+            size += self.free_len.pop(nxt)
+        # merge with the preceding block
+        if i > 0:
+            prv = self.free_starts[i - 1]
+            if prv + self.free_len[prv] == off:
+                self.free_len[prv] += size
+                return
+        self.free_len[off] = size
+        self.free_starts.insert(i, off)
+
+    def largest_free(self) -> int:
+        return max(self.free_len.values(), default=0)
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait(self, until: float) -> None:
+        """Idle until `until` (seconds) at most; short waits spin, longer ones sleep."""
+        dt = until - self.now()
+        if dt > 2e-4:
+            time.sleep(dt - 1e-4)
+
+
+@dataclass
+class Stats:
+    requests: int = 0
+    completed: int = 0
+    rejected: int = 0
+    batches: int = 0
+    cells: int = 0
+    max_queue: int = 0
+    peak_bytes: int = 0
+    latencies: list = field(default_factory=list)
+    first_arrival: float = 0.0
+    last_done: float = 0.0
+    batch_sizes: list = field(default_factory=list)
+
+    def summary(self) -> dict:
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        span = max(self.last_done - self.first_arrival, 1e-9)
+        return {
+            "requests": self.requests, "completed": self.completed, "rejected": self.rejected,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3),
+            "gcells_s": self.cells / span / 1e9,
+            "req_s": self.completed / span,
+            "batches": self.batches,
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "max_queue": self.max_queue, "peak_bytes": self.peak_bytes,
+        }
+
+
+class Server:
+    """The scheduling loop.  executor: launch(batch, offsets) -> handle, done(handle) -> bool,
+    finish(handle) -> [(side, row, col)], release(handle); slots: concurrent launches."""
+
+    def __init__(self, executor, budget_bytes: int, slots: int = 4, max_batch: int = 512,
+                 clock=None, on_complete=None):
+        self.ex = executor
+        self.arena = Arena(budget_bytes)
+        self.slots = int(slots)
+        self.max_batch = int(max_batch)
+        self.clock = clock or WallClock()
+        self.on_complete = on_complete
+
+    def run(self, requests) -> Stats:
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        st = Stats(requests=len(reqs))
+        st.first_arrival = reqs[0].arrival if reqs else 0.0
+        queue = collections.deque()   # arrived, not admitted (FIFO)
+        pending = []        # admitted (memory held), not launched: [(req, bits_off, map_off)]
+        inflight = []       # [(handle, [(req, bits_off, map_off)])]
+        nxt = 0
+        clk = self.clock
+        while nxt < len(reqs) or queue or pending or inflight:
+            now = clk.now()
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                queue.append(reqs[nxt])
+                nxt += 1
+            st.max_queue = max(st.max_queue, len(queue))
+            # completions, in any order
+            still = []
+            for h, items in inflight:
+                if self.ex.done(h):
+                    res = self.ex.finish(h)
+                    t = clk.now()
+                    for (r, boff, moff), rv in zip(items, res):
+                        r.done = t
+                        r.result = tuple(int(v) for v in rv)
+                        if self.on_complete:
+                            self.on_complete(r, self.ex.map_view(h, r, moff))
+                        self.arena.free(boff)
+                        if moff is not None:
+                            self.arena.free(moff)
+                        st.completed += 1
+                        st.cells += r.cells
+                        st.latencies.append(r.done - r.arrival)
+                        st.last_done = max(st.last_done, t)
+                    self.ex.release(h)
+                else:
+                    still.append((h, items))
+            inflight = still
+            # admission: arrival order, while the budget holds the next request
+            while queue and len(pending) < self.max_batch:
+                r = queue[0]
+                if r.device_bytes > self.arena.capacity:
+                    queue.popleft()
+                    r.error = "larger than the HBM budget"
+                    st.rejected += 1
+                    continue
+                boff = self.arena.alloc(r.bits_bytes)
+                if boff is None:
+                    break
+                moff = None
+                if r.want_map:
+                    moff = self.arena.alloc(r.map_bytes)
+                    if moff is None:
+                        self.arena.free(boff)
+                        break
+                queue.popleft()
+                r.admitted = clk.now()
+                pending.append((r, boff, moff))
+            st.peak_bytes = max(st.peak_bytes, self.arena.in_use)
+            # launch everything admitted on a free slot
+            if pending and len(inflight) < self.slots:
+                t = clk.now()
+                for r, _, _ in pending:
+                    r.launched = t
+                h = self.ex.launch(pending)
+                inflight.append((h, pending))
+                st.batches += 1
+                st.batch_sizes.append(len(pending))
+                pending = []
+                continue
+            # nothing to do right now: wait for the next arrival (or poll the device)
+            if nxt < len(reqs) and not inflight and not pending:
+                clk.wait(reqs[nxt].arrival)
+            elif inflight:
+                clk.wait(min(reqs[nxt].arrival if nxt < len(reqs) else float("inf"),
+                             clk.now() + 2e-5))
+        return st
+
+
+class GpuExecutor:
+    """Runs batches through the library on `slots` streams of one device.  One ms_ctx per
+    slot (contexts keep a small scratch that concurrent calls must not share).  The device
+    arena is one allocation of `budget_bytes`; request bits are copied into it from pinned
+    host memory, and maps are written into it."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4, max_batch: int = 512,
+                 max_n: int = 8192, device: int = 0, plain: bool = False):
+        """plain: one ms_max_square launch pair per request instead of the batched call (the
+        one-launch-per-matrix baseline)."""
+        import torch
+        self.plain = bool(plain)
+        from . import Context, lib, _Matrix, ms_batched_workspace_size
+        self.torch = torch
+        self.L = lib()
+        self.dev = torch.device("cuda", device)
+        self.arena = torch.empty(int(budget_bytes) // ALIGN * ALIGN, dtype=torch.uint8,
+                                 device=self.dev)
+        self.base = self.arena.data_ptr()
+        self.slots = []
+        self.max_batch = int(max_batch)
+        msz = ctypes.sizeof(_Matrix)
+        self._Matrix = _Matrix
+        # the workspace bound: every matrix as large as the widest allowed
+        probe = (_Matrix * self.max_batch)()
+        for i in range(self.max_batch):
+            probe[i] = _Matrix(1, max_n, max_n, (max_n + 63) // 64)
+        ws_bytes = ms_batched_workspace_size(None, probe, self.max_batch)
+        for _ in range(int(slots)):
+            self.slots.append({
+                "ctx": Context(device),
+                "stream": torch.cuda.Stream(device=self.dev),
+                "d_mats": torch.empty(self.max_batch * msz, dtype=torch.uint8, device=self.dev),
+                "h_mats": (_Matrix * self.max_batch)(),
+                "h_mats_pinned": torch.empty(self.max_batch * msz, dtype=torch.uint8,
+                                             pin_memory=True),
+                "d_out": torch.empty((self.max_batch, 3), dtype=torch.int64, device=self.dev),
+                "h_out": torch.empty((self.max_batch, 3), dtype=torch.int64, pin_memory=True),
+                "ws": torch.empty(ws_bytes, dtype=torch.uint8, device=self.dev),
+                "ws_bytes": ws_bytes,
+                "event": torch.cuda.Event(),
+                "busy": False,
+            })
+
+    def host_bits(self, bits):
+        """Pinned host copy of a packed matrix (int64 view), for asynchronous uploads."""
+        t = self.torch.from_numpy(np.ascontiguousarray(bits).view(np.int64))
+        return t.pin_memory()
+
+    def launch(self, batch):
+        torch = self.torch
+        slot = next(s for s in self.slots if not s["busy"])
+        slot["busy"] = True
+        if len(batch) > self.max_batch:
+            raise ValueError("batch larger than the executor's max_batch")
+        st = slot["stream"]
+        sp = st.cuda_stream
+        h = slot["h_mats"]
+        with torch.cuda.stream(st):
+            for i, (r, boff, moff) in enumerate(batch):
+                nb = int(r.m) * r.ld_words * 8
+                src = r.bits if isinstance(r.bits, torch.Tensor) else self.host_bits(r.bits)
+                if nb:
+                    self.arena[boff:boff + nb].copy_(src.view(-1).view(torch.uint8)[:nb],
+                                                     non_blocking=True)
+                h[i] = self._Matrix(self.base + boff, r.m, r.n, r.ld_words)
+            count = len(batch)
+            raw = ctypes.string_at(ctypes.addressof(h), ctypes.sizeof(self._Matrix) * count)
+            slot["h_mats_pinned"][:len(raw)].copy_(torch.frombuffer(bytearray(raw),
+                                                                     dtype=torch.uint8))
+            slot["d_mats"][:len(raw)].copy_(slot["h_mats_pinned"][:len(raw)], non_blocking=True)
+            ctx = slot["ctx"].handle
+            if self.plain:
+                for i, (r, boff, moff) in enumerate(batch):
+                    rc = self.L.ms_max_square(ctx, self.base + boff, r.m, r.n, r.ld_words,
+                                              slot["d_out"][i].data_ptr(), sp)
+                    if rc:
+                        raise RuntimeError("ms_max_square failed: %d" % rc)
+            else:
+                rc = self.L.ms_max_square_batched(ctx, h, slot["d_mats"].data_ptr(), count,
+                                                  slot["d_out"].data_ptr(), slot["ws"].data_ptr(),
+                                                  slot["ws_bytes"], sp)
+                if rc:
+                    raise RuntimeError("ms_max_square_batched failed: %d" % rc)
+            for i, (r, boff, moff) in enumerate(batch):
+                if moff is not None and r.cells:
+                    rc = self.L.ms_square_map_from_max(ctx, self.base + boff, r.m, r.n, r.ld_words,
+                                                       slot["d_out"][i].data_ptr(),
+                                                       self.base + moff, r.n, sp)
+                    if rc:
+                        raise RuntimeError("ms_square_map_from_max failed: %d" % rc)
+            slot["h_out"][:count].copy_(slot["d_out"][:count], non_blocking=True)
+            slot["event"].record(st)
+        slot["count"] = count
+        return slot
+
+    def done(self, slot) -> bool:
+        return slot["event"].query()
+
+    def finish(self, slot):
+        rows = slot["h_out"][:slot["count"]].tolist()
+        if any(r[0] < 0 for r in rows):
+            raise RuntimeError("batched call reported an inconsistent batch")
+        return rows
+
+    def map_view(self, slot, r, moff):
+        """The request's dp map as an int32 (m, n) device view; valid until its memory is
+        freed right after the completion callback returns."""
+        if moff is None:
+            return None
+        nb = int(r.m) * int(r.n) * 4
+        return self.arena[moff:moff + nb].view(self.torch.int32).view(int(r.m), int(r.n))
+
+    def release(self, slot):
+        slot["busy"] = False
+
+    def close(self):
+        self.torch.cuda.synchronize(self.dev)
+        for s in self.slots:
+            s["ctx"].close()
+
+
+def poisson_arrivals(count: int, rate: float, seed) -> np.ndarray:
+    """Arrival times (seconds) of an open-loop Poisson client: exponential gaps of mean
+    1 / rate from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=int(count)))
+
+
+def make_requests(pool, count: int, rate: float, map_fraction: float = 0.1, seed=None):
+    """count requests cycling through `pool` ([(bits, m, n), ...]), Poisson arrivals at
+    `rate`, each wanting its map with probability map_fraction."""
+    seed = [30000, int(rate)] if seed is None else seed
+    arr = poisson_arrivals(count, rate, seed)
+    rng = np.random.default_rng([30002, int(rate)])
+    want = rng.random(count) < map_fraction
+    out = []
+    for k in range(count):
+        bits, m, n = pool[k % len(pool)]
+        out.append(Request(rid=k, m=m, n=n, bits=bits, arrival=float(arr[k]),
+                           want_map=bool(want[k])))
+    return out

@@ -2,7 +2,9 @@
 workload, plus a sha256 of the packed input so a consumer can confirm it regenerated the
 same bits.  Calls only the oracle and the input generators.
 
-    python tests/golden/make_golden.py [--only c1,c2,c3a,c3b,c3c]
+    python tests/golden/make_golden.py [--only c1,c2,c3a,c3b,c3c,c4]
+
+The batched workload's 10000 results go to c4_results.txt instead (one line per matrix).
 """
 import argparse
 import hashlib
@@ -18,6 +20,7 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_configs.json")
+OUT_C4 = os.path.join(HERE, "c4_results.txt")
 
 
 def sha(bits):
@@ -31,6 +34,27 @@ def record(name, bits, m, n, extra=None):
     rec.update(extra or {})
     print(name, rec, "%.1fs" % (time.time() - t), flush=True)
     return rec
+
+
+def write_c4(count=10000):
+    """Oracle (side, row, col) for every matrix of the batched workload, and a sha256 over
+    all packed inputs in order."""
+    from concurrent.futures import ThreadPoolExecutor
+    t = time.time()
+    mats, m, n, p = W.batch_packed(count)
+    h = hashlib.sha256()
+    for a in mats:
+        h.update(a.tobytes())
+    with ThreadPoolExecutor(8) as ex:   # the oracle's C call releases the GIL
+        res = list(ex.map(lambda k: oracle.max_square_packed(mats[k], int(n[k])), range(count)))
+    with open(OUT_C4, "w") as f:
+        f.write("# Written by tests/golden/make_golden.py from the oracle only.\n")
+        f.write("# batched workload: %d matrices, sha256 of the packed inputs in order %s\n"
+                % (count, h.hexdigest()))
+        f.write("# index m n side row col\n")
+        for k, (s_, r_, c_) in enumerate(res):
+            f.write("%d %d %d %d %d %d\n" % (k, m[k], n[k], s_, r_, c_))
+    print("c4", count, "matrices, %.1fs" % (time.time() - t), flush=True)
 
 
 def main():
@@ -49,20 +73,19 @@ def main():
             grid["%d_%d" % (n, d)] = record("c2 %d %.1f" % (n, p), W.gen_bernoulli_packed(n, n, p, seed),
                                            n, n, {"p": p, "seed": seed})
         data["c2"] = grid
-    if "c3a" in want:
-        data["c3a"] = record("c3a", W.gen_bernoulli_packed(32768, 32768, 0.9, 1), 32768, 32768,
-                             {"p": 0.9, "seed": 1})
-    if "c3b" in want:
-        bits, r0, c0 = W.gen_planted_packed(4096, 262144, 0.5, 1500, 2)
-        data["c3b"] = record("c3b", bits, 4096, 262144, {"p": 0.5, "seed": 2, "planted": [r0, c0, 1500]})
-        del bits
-    if "c3c" in want:
-        a = W.gen_blob(16384, 16384, 8.0, 60.0, 3)
-        dens = float(a.mean())
-        bits = W.pack_rows(a)
-        del a
-        data["c3c"] = record("c3c", bits, 16384, 16384, {"sigma": 8.0, "percentile": 60.0, "seed": 3,
-                                                          "density": dens})
+    for name in ("c3a", "c3b", "c3c"):
+        if name in want:
+            bits, m, n, extra = W.large_packed(name)
+            extra = dict(extra)
+            for k, v in W.LARGE[name].items():
+                if k not in ("m", "n", "side"):
+                    extra[k] = v
+            if name == "c3c":
+                extra["density"] = float(W.unpack_rows(bits, n).mean())
+            data[name] = record(name, bits, m, n, extra)
+            del bits
+    if "c4" in want:
+        write_c4()
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
 

@@ -95,3 +95,34 @@ def test_batched_graph_replays(dev, monkeypatch):
         d, n = items[k]
         single = M.max_square(d, n)       # eager work between replays
         assert (single.side, single.row, single.col) == refs[k]
+
+
+def test_batched_graph_same_buffers_new_shapes(dev, monkeypatch):
+    """Graph mode with the descriptor buffer, count, output and workspace reused for a batch
+    of different shapes: the second call must not replay the first call's launch sequence."""
+    import ctypes
+    import torch
+    announce("batched graph new shapes")
+    monkeypatch.setenv("MAXSQ_GRAPH", "1")
+    sets = [make_mix(6, 10), make_mix(7, 10)]
+    items = [[(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in s] for s in sets]
+    count = 10
+    h = [(M._Matrix * count)() for _ in sets]
+    for k in range(2):
+        for i, (bits, n) in enumerate(items[k]):
+            h[k][i] = M._Matrix(bits.data_ptr(), bits.size(0), n, M._ld_words(bits, n))
+    ws_bytes = max(M.ms_batched_workspace_size(None, h[k], count) for k in range(2))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    d_mats = torch.empty(ctypes.sizeof(M._Matrix) * count, dtype=torch.uint8, device=dev)
+    out = torch.empty((count, 3), dtype=torch.int64, device=dev)
+    sp = torch.cuda.current_stream().cuda_stream
+    for rep in range(2):
+        for k in range(2):
+            raw = bytes(h[k])
+            d_mats.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
+            out.fill_(-7)
+            rc = M.ms_max_square_batched(None, h[k], d_mats.data_ptr(), count, out.data_ptr(),
+                                         ws.data_ptr(), ws_bytes, sp)
+            assert rc == 0
+            got = [tuple(r) for r in out.cpu().tolist()]
+            assert got == [oracle.max_square(a) for a in sets[k]], (rep, k)

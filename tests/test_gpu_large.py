@@ -20,13 +20,10 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracl
 
 def make_input(name):
     g = GOLDEN[name]
-    if name == "c3a":
-        bits = W.gen_bernoulli_packed(g["m"], g["n"], g["p"], g["seed"])
-    elif name == "c3b":
-        bits, r0, c0 = W.gen_planted_packed(g["m"], g["n"], g["p"], g["planted"][2], g["seed"])
-        assert [r0, c0] == g["planted"][:2]
-    else:
-        bits = W.pack_rows(W.gen_blob(g["m"], g["n"], g["sigma"], g["percentile"], g["seed"]))
+    bits, m, n, extra = W.large_packed(name)
+    assert (m, n) == (g["m"], g["n"])
+    if "planted" in extra:
+        assert extra["planted"] == g["planted"]
     assert hashlib.sha256(bits.tobytes()).hexdigest() == g["sha256_packed"], "input differs"
     return bits, g
 
@@ -63,3 +60,31 @@ def test_large_config(dev, name):
                 r0 + bad[0], bad[1], got[tuple(bad)], ref[tuple(bad)]))
     assert st.result() == (g["side"], g["row"], g["col"])
     announce("large", name, "map verified in %.1fs" % (time.time() - t3))
+
+
+def test_c4_batched_full(dev):
+    """All 10000 matrices of the batched workload in one batched call, and each through the
+    plain single-matrix call, against the oracle's stored results."""
+    import torch
+    path = os.path.join(os.path.dirname(__file__), "golden", "c4_results.txt")
+    lines = open(path).read().splitlines()
+    ref = np.array([[int(x) for x in ln.split()] for ln in lines if not ln.startswith("#")])
+    announce("large", "c4", "generating %d matrices" % len(ref))
+    mats, m, n, _ = W.batch_packed(len(ref))
+    h = hashlib.sha256()
+    for a in mats:
+        h.update(a.tobytes())
+    assert h.hexdigest() == lines[1].split()[-1], "inputs differ"
+    assert np.array_equal(ref[:, 1], m) and np.array_equal(ref[:, 2], n)
+    items = [(torch.from_numpy(a.view(np.int64)).to(dev), int(nn)) for a, nn in zip(mats, n)]
+    announce("large", "c4", "batched")
+    got = np.array([[s.side, s.row, s.col] for s in M.max_square_batched(items)])
+    bad = np.flatnonzero(np.any(got != ref[:, 3:6], axis=1))
+    assert bad.size == 0, "matrix %d: %s vs oracle %s" % (bad[0], got[bad[0]], ref[bad[0], 3:6])
+    announce("large", "c4", "plain per-matrix calls")
+    res = torch.empty((len(ref), 3), dtype=torch.int64, device=dev)
+    for k, (d, nn) in enumerate(items):
+        M.max_square(d, nn, out=res[k], sync=False)
+    got = np.array(res.cpu().tolist())
+    bad = np.flatnonzero(np.any(got != ref[:, 3:6], axis=1))
+    assert bad.size == 0, "matrix %d: %s vs oracle %s" % (bad[0], got[bad[0]], ref[bad[0], 3:6])

@@ -1,0 +1,235 @@
+"""The serving loop's scheduling logic on the CPU: a virtual clock and a simulated device whose
+results come from the oracle.  Covers the arena, open-loop arrivals, HBM-budget admission,
+continuous batching, slot limits, rejection of oversized requests and the latency figures."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2503_18974_amd.serve import (ALIGN, Arena, Request, Server, make_requests,
+                                        poisson_arrivals)
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def wait(self, until):
+        self.t = max(self.t, until)
+
+
+class FakeExecutor:
+    """Completes a batch `base + per_cell * cells` seconds after launch; results from the
+    oracle.  Records what was live on the device at every launch."""
+
+    def __init__(self, clock, arena_ref, base=1e-4, per_cell=1e-10):
+        self.clock = clock
+        self.arena_ref = arena_ref
+        self.base = base
+        self.per_cell = per_cell
+        self.launches = []
+        self.live_slots = 0
+        self.max_live_slots = 0
+
+    def launch(self, batch):
+        cells = sum(r.cells for r, _, _ in batch)
+        h = {"t": self.clock.now() + self.base + self.per_cell * cells, "batch": list(batch)}
+        self.launches.append((self.clock.now(), [r.rid for r, _, _ in batch],
+                              self.arena_ref().in_use))
+        self.live_slots += 1
+        self.max_live_slots = max(self.max_live_slots, self.live_slots)
+        return h
+
+    def done(self, h):
+        return self.clock.now() >= h["t"]
+
+    def finish(self, h):
+        return [oracle.max_square_packed(np.asarray(r.bits), r.n) for r, _, _ in h["batch"]]
+
+    def map_view(self, h, r, moff):
+        return None if moff is None else ("map", r.rid)
+
+    def release(self, h):
+        self.live_slots -= 1
+
+
+def make_server(budget, slots=2, max_batch=64, base=1e-4, per_cell=1e-10, on_complete=None):
+    clk = VirtualClock()
+    holder = {}
+    ex = FakeExecutor(clk, lambda: holder["s"].arena, base, per_cell)
+    s = Server(ex, budget, slots=slots, max_batch=max_batch, clock=clk, on_complete=on_complete)
+    holder["s"] = s
+    return s, ex, clk
+
+
+def small_pool(count, seed=0, lo=8, hi=300):
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(count):
+        m, n = int(rng.integers(lo, hi)), int(rng.integers(lo, hi))
+        bits = W.gen_bernoulli_packed(m, n, float(rng.uniform(0.3, 0.95)), [77, seed, k])
+        pool.append((bits, m, n))
+    return pool
+
+
+# ------------------------------------------------------------------------------ arena
+
+def test_arena_first_fit_and_coalescing():
+    a = Arena(10 * ALIGN)
+    x = a.alloc(3 * ALIGN)
+    y = a.alloc(1)
+    z = a.alloc(4 * ALIGN)
+    assert (x, y, z) == (0, 3 * ALIGN, 4 * ALIGN)
+    assert a.in_use == 8 * ALIGN
+    assert a.alloc(3 * ALIGN) is None            # only 2 units left
+    a.free(y)
+    assert a.alloc(2 * ALIGN) == 8 * ALIGN       # first fit skips the 1-unit hole
+    a.free(x)
+    a.free(z)                                    # x, y holes and z merge into one block
+    assert a.largest_free() == 8 * ALIGN
+    assert a.alloc(8 * ALIGN) == 0
+    assert a.peak == 10 * ALIGN
+
+
+def test_arena_random_never_overlaps():
+    rng = np.random.default_rng(1)
+    a = Arena(1 << 20)
+    live = {}
+    for _ in range(3000):
+        if live and rng.random() < 0.45:
+            off = list(live)[int(rng.integers(len(live)))]
+            a.free(off)
+            del live[off]
+        else:
+            sz = int(rng.integers(1, 40000))
+            off = a.alloc(sz)
+            if off is not None:
+                live[off] = -(-sz // ALIGN) * ALIGN
+        spans = sorted(live.items())
+        for (o1, s1), (o2, _) in zip(spans, spans[1:]):
+            assert o1 + s1 <= o2
+        assert all(o + s <= a.capacity for o, s in spans)
+        assert a.in_use == sum(live.values())
+    for off in list(live):
+        a.free(off)
+    assert a.largest_free() == a.capacity and a.in_use == 0
+
+
+# ------------------------------------------------------------------------------ loop
+
+def test_results_equal_oracle_and_all_complete():
+    pool = small_pool(12)
+    reqs = make_requests(pool, 60, rate=2000.0, map_fraction=0.2)
+    s, ex, clk = make_server(budget=1 << 22)
+    st = s.run(reqs)
+    assert st.completed == 60 and st.rejected == 0
+    for r in reqs:
+        assert r.result == oracle.max_square_packed(np.asarray(r.bits), r.n)
+        assert r.arrival <= r.admitted <= r.launched < r.done
+
+
+def test_budget_is_never_exceeded_and_large_requests_wait():
+    pool = small_pool(8, seed=2, lo=100, hi=400)
+    reqs = make_requests(pool, 40, rate=1e5, map_fraction=0.5)
+    need = max(r.device_bytes for r in reqs)
+    budget = need * 2                      # room for about two requests at a time
+    s, ex, clk = make_server(budget=budget, slots=4, per_cell=1e-8)
+    st = s.run(reqs)
+    assert st.completed == 40
+    assert st.peak_bytes <= s.arena.capacity
+    assert all(in_use <= s.arena.capacity for _, _, in_use in ex.launches)
+    # memory pressure forces requests to wait for earlier completions
+    waited = [r for r in reqs if r.admitted > r.arrival]
+    assert waited
+    order = sorted(reqs, key=lambda r: r.arrival)
+    assert [r.rid for r in sorted(reqs, key=lambda r: (r.admitted, r.rid))] == \
+        [r.rid for r in order]     # admission is first come, first served
+
+
+def test_oversized_request_is_rejected_and_others_complete():
+    pool = small_pool(4, seed=3)
+    reqs = make_requests(pool, 10, rate=1000.0, map_fraction=0.0)
+    big_bits = W.gen_bernoulli_packed(2000, 2000, 0.5, 9)
+    reqs.append(Request(rid=99, m=2000, n=2000, bits=big_bits, arrival=0.001, want_map=True))
+    s, ex, clk = make_server(budget=1 << 20)
+    st = s.run(reqs)
+    assert st.rejected == 1 and st.completed == 10
+    big = [r for r in reqs if r.rid == 99][0]
+    assert big.error and big.result is None
+
+
+def test_continuous_batching_joins_arrivals_during_flight():
+    pool = small_pool(6, seed=4)
+    reqs = make_requests(pool, 200, rate=50000.0, map_fraction=0.0)
+    s, ex, clk = make_server(budget=1 << 24, slots=1, base=5e-4)
+    st = s.run(reqs)
+    assert st.completed == 200
+    # with one slot busy for 0.5 ms per batch, later batches carry the arrivals meanwhile
+    assert st.batches < 200 and max(st.batch_sizes) > 1
+    for t_launch, rids, _ in ex.launches:
+        for rid in rids:
+            assert reqs[rid].arrival <= t_launch
+    assert ex.max_live_slots == 1
+
+
+def test_slots_bound_concurrency():
+    pool = small_pool(6, seed=5)
+    reqs = make_requests(pool, 120, rate=1e5, map_fraction=0.0)
+    s, ex, clk = make_server(budget=1 << 24, slots=3, max_batch=4, base=1e-3)
+    st = s.run(reqs)
+    assert st.completed == 120
+    assert ex.max_live_slots == 3
+    assert max(st.batch_sizes) <= 4
+
+
+def test_open_loop_latency_grows_when_overloaded():
+    pool = small_pool(4, seed=6)
+    light = make_requests(pool, 100, rate=100.0, map_fraction=0.0)
+    heavy = make_requests(pool, 100, rate=1e5, map_fraction=0.0)
+    st_l = make_server(budget=1 << 24, slots=1, max_batch=1, base=1e-3)[0].run(light)
+    st_h = make_server(budget=1 << 24, slots=1, max_batch=1, base=1e-3)[0].run(heavy)
+    sl, sh = st_l.summary(), st_h.summary()
+    assert sl["p50_ms"] < 1.1          # each request alone takes ~1 ms; at 100/s about one
+    assert sl["p99_ms"] < 3.1          # gap in ten is shorter than that, so p99 queues briefly
+    assert sh["p99_ms"] > 50           # the queue builds: ~100 x 1 ms
+    assert st_h.max_queue > 10
+
+
+def test_latency_percentiles():
+    pool = small_pool(2, seed=7)
+    reqs = make_requests(pool, 50, rate=10.0, map_fraction=0.0)   # never overlapping
+    st = make_server(budget=1 << 24, base=2e-3, per_cell=0.0)[0].run(reqs)
+    s = st.summary()
+    assert abs(s["p50_ms"] - 2.0) < 0.05 and abs(s["p99_ms"] - 2.0) < 0.05
+    assert s["completed"] == 50 and s["req_s"] > 0 and s["gcells_s"] > 0
+
+
+def test_map_views_reach_the_callback():
+    pool = small_pool(5, seed=8)
+    reqs = make_requests(pool, 40, rate=3000.0, map_fraction=0.5)
+    seen = {}
+    s, ex, clk = make_server(budget=1 << 24, on_complete=lambda r, v: seen.__setitem__(r.rid, v))
+    s.run(reqs)
+    assert set(seen) == {r.rid for r in reqs}
+    for r in reqs:
+        assert (seen[r.rid] is not None) == r.want_map
+
+
+def test_poisson_arrivals():
+    t = poisson_arrivals(20000, 5000.0, [30000, 5000])
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert np.all(gaps > 0)
+    assert abs(gaps.mean() - 1 / 5000.0) < 0.03 / 5000.0
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05        # exponential: cv = 1
+    assert np.array_equal(t, poisson_arrivals(20000, 5000.0, [30000, 5000]))
+
+
+def test_request_pool_recipe():
+    bits, m, n, kind, params = W.serving_request(3)
+    assert 32 <= m <= 8192 and 32 <= n <= 8192 and bits.shape == (m, (n + 63) // 64)
+    kinds = [W.serving_request(k, hi=128)[3] for k in range(200)]
+    frac = kinds.count("bernoulli") / len(kinds)
+    assert 0.6 < frac < 0.8

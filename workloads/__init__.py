@@ -23,7 +23,7 @@ import numpy as np
 __all__ = [
     "words_per_row", "pack_rows", "unpack_rows", "gen_bernoulli", "gen_bernoulli_packed",
     "gen_planted_packed", "gen_blob", "paper_grid", "paper_grid_seed", "c1", "batch_shapes",
-    "gen_batch_matrix", "CHUNK_ROWS",
+    "gen_batch_matrix", "batch_packed", "large_packed", "LARGE", "serving_request", "CHUNK_ROWS",
 ]
 
 CHUNK_ROWS = 256
@@ -144,6 +144,39 @@ def batch_shapes(count: int = 10000, lo: int = 16, hi: int = 4096, seed: int = 1
 def gen_batch_matrix(i: int, m: int, n: int, p: float, seed: int = 10000) -> np.ndarray:
     """Matrix i of the batched workload, packed."""
     return gen_bernoulli_packed(int(m), int(n), float(p), [seed, int(i)])
+
+
+def batch_packed(count: int = 10000, threads: int = 16, seed: int = 10000):
+    """The whole batched workload, packed: (list of packed matrices, m, n, p).  Matrices are
+    independent streams, so a thread pool draws them in parallel with the same bits."""
+    from concurrent.futures import ThreadPoolExecutor
+    m, n, p = batch_shapes(count, seed=seed)
+    with ThreadPoolExecutor(max(1, int(threads))) as ex:
+        mats = list(ex.map(lambda i: gen_batch_matrix(i, m[i], n[i], p[i], seed), range(count)))
+    return mats, m, n, p
+
+
+# The large single matrices: (a) 32768^2 Bernoulli(0.9), seed 1; (b) 4096 x 262144
+# Bernoulli(0.5), seed 2, with an all-ones 1500^2 block planted at a position drawn after the
+# noise; (c) 16384^2 blob image, sigma 8 px, threshold at the 60th percentile, seed 3.
+LARGE = {
+    "c3a": {"m": 32768, "n": 32768, "p": 0.9, "seed": 1},
+    "c3b": {"m": 4096, "n": 262144, "p": 0.5, "seed": 2, "side": 1500},
+    "c3c": {"m": 16384, "n": 16384, "sigma": 8.0, "percentile": 60.0, "seed": 3},
+}
+
+
+def large_packed(name: str):
+    """(packed bits, m, n, extra) for one of the LARGE matrices; extra holds the planted
+    block's [row, col, side] for c3b."""
+    c = LARGE[name]
+    if name == "c3a":
+        return gen_bernoulli_packed(c["m"], c["n"], c["p"], c["seed"]), c["m"], c["n"], {}
+    if name == "c3b":
+        bits, r0, c0 = gen_planted_packed(c["m"], c["n"], c["p"], c["side"], c["seed"])
+        return bits, c["m"], c["n"], {"planted": [r0, c0, c["side"]]}
+    a = gen_blob(c["m"], c["n"], c["sigma"], c["percentile"], c["seed"])
+    return pack_rows(a), c["m"], c["n"], {}
 
 
 def serving_request(k: int, lo: int = 32, hi: int = 8192, seed: int = 30001):
