@@ -60,9 +60,10 @@ uint64_t shape_hash(const ms_matrix *h_mats, int64_t count) {
 struct ms_ctx {
     int device = 0;
     int num_cus = 256;
-    // single-matrix scratch: header | serial-pass state
+    // single-matrix scratch: header | serial-pass state | one saturation byte per probe tile
     void *scratch = nullptr;
     int64_t state_words = 0;
+    int64_t sat_bytes = 0;
     bool dirty = false;
     bool has_forced = false;
     ms_config forced{};
@@ -146,10 +147,12 @@ bool config_valid(const ms_config &cfg) {
            cfg.map_band_rows <= (1 << 20);
 }
 
-// Make sure the context scratch holds the serial-pass state for an m x n matrix.
-ms_status ensure_scratch(ms_ctx *c, int64_t n, hipStream_t stream) {
+// Make sure the context scratch holds the serial-pass state and the probe's saturation bytes
+// for an m x n matrix.
+ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     const int64_t nwords = std::max<int64_t>(1, cdiv(n, 64));
-    if (c->scratch && c->state_words >= nwords) {
+    const int64_t tiles = mshost::max_probe_tiles(m, n);
+    if (c->scratch && c->state_words >= nwords && c->sat_bytes >= tiles) {
         if (c->dirty) {
             if (hipMemsetAsync(c->scratch, 0, sizeof(mshost::ScratchHeader), stream) != hipSuccess)
                 return MS_ERR_HIP;
@@ -158,7 +161,9 @@ ms_status ensure_scratch(ms_ctx *c, int64_t n, hipStream_t stream) {
         return MS_OK;
     }
     const int64_t words = std::max<int64_t>(nwords, c->state_words);
-    const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t);
+    const int64_t sat = std::max<int64_t>(tiles, c->sat_bytes);
+    const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t) +
+                         (size_t)sat;
     if (c->scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
@@ -173,11 +178,16 @@ ms_status ensure_scratch(ms_ctx *c, int64_t n, hipStream_t stream) {
     }
     c->scratch = p;
     c->state_words = words;
+    c->sat_bytes = sat;
     c->dirty = false;
     return MS_OK;
 }
 
 mshost::ScratchHeader *hdr_of(ms_ctx *c) { return static_cast<mshost::ScratchHeader *>(c->scratch); }
+uint8_t *sat_of(ms_ctx *c) {
+    return static_cast<uint8_t *>(c->scratch) + sizeof(mshost::ScratchHeader) +
+           (size_t)c->state_words * 64 * 2 * sizeof(int32_t);
+}
 int32_t *state_of(ms_ctx *c) {
     return reinterpret_cast<int32_t *>(static_cast<char *>(c->scratch) +
                                        sizeof(mshost::ScratchHeader));
@@ -197,7 +207,7 @@ ms_status validate_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t ld
 ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, int64_t m,
                          int64_t n, int64_t ldw, ms_square *out, hipStream_t stream) {
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
-    ms_status s = ensure_scratch(c, n, stream);
+    ms_status s = ensure_scratch(c, m, n, stream);
     if (s != MS_OK) return s;
     mshost::LaunchEnv env{c->num_cus, stream};
     hipError_t e;
@@ -205,7 +215,7 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
         e = mshost::launch_write_result(env, out, hdr_of(c), out ? 1 : 0);
     } else {
         e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
-                                      state_of(c), out);
+                                      state_of(c), sat_of(c), out);
     }
     if (e != hipSuccess) {
         c->dirty = true;
@@ -335,7 +345,7 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
     const ms_config cfg = config_for(c, m, n);
     hipStream_t st = (hipStream_t)stream;
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
-    s = ensure_scratch(c, n, st);
+    s = ensure_scratch(c, m, n, st);
     if (s != MS_OK) return s;
     mshost::LaunchEnv env{c->num_cus, st};
     return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m,

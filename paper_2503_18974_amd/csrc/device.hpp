@@ -438,55 +438,38 @@ __device__ __forceinline__ bool any_owned(const uint64_t (&T)[TS::RPL], int rg, 
     return __ballot(lane_ok && acc != 0) != 0;
 }
 
-constexpr int EX_NG = 8;    // exact pass window: 8 groups x 256 columns
-constexpr int EX_CPL = 4;
-
 // Where the outcome of one tile goes.
 struct TileSink {
-    unsigned long long *key;   // atomicMax target
-    uint32_t *serial_flag;     // set when a square is too wide for the exact pass's window
-    WaveLds lds;               // this wave's LDS staging area (exact pass)
+    unsigned long long *key;   // atomicMax target: (side, first position) of the best square
 };
 
-// Exact largest square among the owned cells [ra, rb) x [xa, xb) of a saturated tile (whose
-// side is known to be >= kmin): dprun with a halo U that doubles until the local maximum M
-// satisfies M <= U, which proves every owned value exact.  Returns false if the halo would
-// exceed the widest window (the caller then falls back to the serial pass).
-template <int NGMAX, int CPL>
-__device__ bool exact_region(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
-                             int64_t ra, int64_t rb, int64_t xa, int64_t xb, int64_t kmin,
-                             Track &out, WaveLds lds) {
-    constexpr int64_t WIN = (int64_t)NGMAX * 64 * CPL;
-    (void)m;
-    int64_t U = 2 * kmin;
-    for (;;) {
-        const int64_t hc = (U + 63) & ~(int64_t)63;
-        if (hc + 64 > WIN) return false;
-        const int64_t ow = WIN - hc;
-        const int64_t rh = ra - U > 0 ? ra - U : 0;
-        Track tr{0, INT64_MAX};
-        for (int64_t xa_w = xa; xa_w < xb; xa_w += ow) {
-            const int64_t xb_w = xa_w + ow < xb ? xa_w + ow : xb;
-            const int64_t xh_w = xa_w - hc > 0 ? ((xa_w - hc) & ~(int64_t)63) : 0;
-            const int ngw = (int)((xb_w - xh_w + 64 * CPL - 1) / (64 * CPL));
-            dprun<NGMAX, CPL, false, true>(bits, ldw, n, rh, ra, rb, xh_w, xa_w, xb_w, ngw,
-                                           nullptr, 0, false, tr, lds);
-        }
-        Track w = wave_track(tr);
-        if (w.v <= U) {
-            out = w;
-            return true;
-        }
-        U = 2 * (int64_t)w.v;
+// Saturation bytes of the tiles a wave visits (tile t0 + k * stride for k < 64), written with
+// one store per 64 tiles: a store per tile would make the next tile's loads wait for it.
+struct SatBatch {
+    uint8_t *base;
+    int64_t t0 = 0, stride = 1;
+    uint64_t bits = 0;
+    int count = 0, nsat = 0;
+    __device__ void add(int64_t t, bool s) {
+        const int32_t su = uniform((int32_t)s);   // wave-uniform: keep the state in SGPRs
+        if (count == 0) t0 = uniform(t);
+        bits |= (uint64_t)su << count;
+        nsat += su;
+        if (++count == 64) flush();
     }
-}
-
+    __device__ void flush() {
+        const int lane = __lane_id();
+        if (lane < count) base[t0 + lane * stride] = (uint8_t)((bits >> lane) & 1);
+        bits = 0;
+        count = 0;
+    }
+};
 
 // Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
-// key with the first owned cell of E_k.  A tile whose E_KC is non-empty is "saturated": its
-// exact side comes from the dp pass with a doubling halo, run by the same wave.
+// key with the first owned cell of E_k.  Returns whether E_KC is non-empty among the owned cells
+// ("saturated": the resolve pass, resolve_tile, finishes such a tile).
 template <class TS>
-__device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+__device__ __forceinline__ bool tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int64_t ty, int64_t tx, const TileSink &sink) {
     constexpr int RPL = TS::RPL;
     m = uniform(m);
@@ -519,7 +502,7 @@ __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_
     const bool lane_ok = wl != 0 && wvalid;
     // best side found so far by any tile (read now so the load overlaps the erosion steps)
     const int64_t best = key_side(load_relaxed(sink.key));
-    if (!any_owned<TS>(E, rg, lane_ok)) return;
+    if (!any_owned<TS>(E, rg, lane_ok)) return false;
 
     int cur = 1;
     bool saturated = true;
@@ -536,7 +519,7 @@ __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_
     }
     if (!saturated) {
         // the tile's side is in [cur, 2 cur - 1]; skip it if it cannot reach the best so far
-        if (2 * cur - 1 < best) return;
+        if (2 * cur - 1 < best) return false;
         for (int d = cur >> 1; d >= 1; d >>= 1) {
             erode_by<RPL>(E, T, d, rg, wl);
             if (any_owned<TS>(T, rg, lane_ok)) {
@@ -544,9 +527,9 @@ __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_
                 for (int r = 0; r < RPL; ++r) E[r] = T[r];
                 cur += d;
             }
-            if (cur + d - 1 < best) return;
+            if (cur + d - 1 < best) return false;
         }
-        if (cur < best) return;
+        if (cur < best) return false;
     }
     // first owned cell of E_cur in row-major order
     int64_t pos = INT64_MAX;
@@ -560,18 +543,261 @@ __device__ void tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_
     }
     pos = wave_min_i64(pos);
     if (lane == 0) atomicMax(sink.key, make_key(cur, pos));
-    if (saturated) {
-        // the tile holds a square of side KC or more: its exact side and first corner come from
-        // the windowed dp pass over its owned cells
-        const int64_t ra = ty * TS::TR, rb = ra + TS::TR < m ? ra + TS::TR : m;
-        const int64_t xa = tx * TS::OWN_WORDS * 64;
-        const int64_t xb = xa + TS::OWN_WORDS * 64 < n ? xa + TS::OWN_WORDS * 64 : n;
-        Track t{0, INT64_MAX};
-        if (exact_region<EX_NG, EX_CPL>(bits, m, n, ldw, ra, rb, xa, xb, TS::KC, t, sink.lds)) {
-            if (lane == 0 && t.v > 0) atomicMax(sink.key, make_key(t.v, t.pos));
-        } else if (lane == 0) {
-            atomicOr(sink.serial_flag, 1u);
+    return saturated;
+}
+
+// ----------------------------------------------------------------------------------------------
+// resolve_tile: the exact largest side and first corner of a saturated tile, computed with the
+// paper's frequency array instead of a dp halo.
+//
+// Bound.  A square of side s >= KC whose bottom-right cell (i, j) lies in the tile puts an E_KC
+// cell at (i', j) for every i - s + KC <= i' <= i and at (i, j') for every j - s + KC <= j' <= j,
+// so every tile holding one of them is saturated:
+//     s <= U = min(Vrun * TR, Hrun * 64 * OWN_WORDS) + KC - 1,
+// with Vrun / Hrun the runs of consecutive saturated tiles ending at this one in its tile column
+// and tile row.
+//
+// Search.  H (run of ones ending at each cell down its column, the paper's freq) is built at the
+// row above the tile by scanning at most U rows upwards (U is the bound above when one pass can
+// hold it, else it doubles from twice the best side so far until the tile's result is below U
+// or U reaches the bound), over the tile's columns
+// and the U columns to their left, and kept bit-sliced: plane p holds bit p of H for the 64 columns of a
+// lane's word.  A cell has dp >= k iff the k columns ending at it all have H >= k (the side map
+// in its rows-independent form), i.e. iff the horizontal erosion by k of the mask (H >= k) holds
+// it.  As in Algorithm 1 the best side over the rows seen so far grows by at most one per row
+// (dp[i][j] <= dp[i-1][j] + 1), so the tile's first row gets a gallop-and-bisect search over k
+// and each later row a single test of k = best + 1.  The first row reaching the final best, and
+// its first column there, give the tile's first corner in row-major order.
+// ----------------------------------------------------------------------------------------------
+constexpr int HB = 12;  // bit planes of H: heights up to 4095 (U + TR stays below)
+
+__device__ __forceinline__ void planes_inc_masked(uint64_t (&P)[HB], uint64_t c) {
+#pragma unroll
+    for (int p = 0; p < HB; ++p) {
+        const uint64_t t = P[p] & c;
+        P[p] ^= c;
+        c = t;
+    }
+}
+
+// Mask of the columns whose H >= k (k wave-uniform).
+__device__ __forceinline__ uint64_t planes_ge(const uint64_t (&P)[HB], int32_t k) {
+    uint64_t gt = 0, eq = ~0ull;
+#pragma unroll
+    for (int p = HB - 1; p >= 0; --p) {
+        if ((k >> p) & 1) {
+            eq &= P[p];
+        } else {
+            gt |= eq & P[p];
+            eq &= ~P[p];
         }
+    }
+    return gt | eq;
+}
+
+// Lane l receives lane l-1's 64-bit value, lane 0 receives 0 (two DPP moves).
+__device__ __forceinline__ uint64_t from_left_lane64(uint64_t v) {
+    const uint32_t lo = (uint32_t)from_left_lane((int32_t)(uint32_t)v, 0);
+    const uint32_t hi = (uint32_t)from_left_lane((int32_t)(uint32_t)(v >> 32), 0);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A row bitmask held one word per lane (lane l: word w0 + l).  Bit j of the result is bit j - t
+// of v's row; columns left of the window read 0.  Word offsets 0 and 1 (t < 128) move through
+// DPP; larger ones through a lane permute.
+__device__ __forceinline__ uint64_t row_from_left(uint64_t v, int32_t t, int lane) {
+    const int q = t >> 6, r = t & 63;
+    uint64_t a, b;
+    if (q == 0) {
+        a = v;
+        b = from_left_lane64(v);
+    } else if (q == 1) {
+        a = from_left_lane64(v);
+        b = from_left_lane64(a);
+    } else {
+        const uint64_t pa = __shfl(v, lane - q);
+        const uint64_t pb = __shfl(v, lane - q - 1);
+        a = lane - q >= 0 ? pa : 0ull;
+        b = lane - q - 1 >= 0 ? pb : 0ull;
+    }
+    return r ? ((a << r) | (b >> (64 - r))) : a;
+}
+
+// Bit j set iff bits j - k + 1 .. j of v's row are all set (log-doubling shift-AND).
+__device__ __forceinline__ uint64_t row_erode(uint64_t v, int32_t k, int lane) {
+    int32_t a = 1;
+    while (2 * a <= k) {
+        v &= row_from_left(v, a, lane);
+        a <<= 1;
+    }
+    if (k > a) v &= row_from_left(v, k - a, lane);
+    return v;
+}
+
+// Does an owned cell of the current row have dp >= k?  If so, *col = the first such column.
+__device__ __forceinline__ bool row_test(const uint64_t (&P)[HB], int32_t k, uint64_t own,
+                                         int lane, int64_t w0, int64_t *col) {
+    const uint64_t y = row_erode(planes_ge(P, k), k, lane) & own;
+    const uint64_t b = __ballot(y != 0);
+    if (!b) return false;
+    const int fl = __ffsll((long long)b) - 1;
+    const uint64_t yf = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(y >> 32), fl) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)y, fl);
+    *col = (w0 + fl) * 64 + (__ffsll((long long)yf) - 1);
+    return true;
+}
+
+// Consecutive set saturation bytes at idx0, idx0 - step, idx0 - 2 step, ... (idx0 - k step >= 0
+// while k < limit), 64 per round.
+__device__ __forceinline__ int64_t sat_run(const uint8_t *__restrict__ sat, int64_t idx0,
+                                           int64_t step, int64_t limit, int lane) {
+    int64_t run = 0;
+    for (;;) {
+        const int64_t k = run + lane;
+        const bool s = k < limit && sat[idx0 - k * step] != 0;
+        const uint64_t b = __ballot(s);
+        const int c = (~b) ? __ffsll((long long)~b) - 1 : 64;
+        run += c;
+        if (c < 64) return run;
+    }
+}
+
+// One pass over the tile with heights clamped at depth U and a window of U columns to the left
+// of the tile: *best / *bpos receive the tile's largest computed side and its first cell.  A
+// true side s >= U still computes as >= U (clamping and clipping cannot push a value below U),
+// so a result below U is exact.  Returns false if the window exceeds one word per lane.
+template <class TS>
+__device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
+                             int64_t ldw, int64_t ty, int64_t tx, int64_t U, int32_t *best_out,
+                             int64_t *bpos_out) {
+    constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
+    const int lane = __lane_id();
+    const int64_t ra = ty * TS::TR, rb = ra + TS::TR < m ? ra + TS::TR : m;
+    const int64_t xa = tx * OWN_COLS, xb = xa + OWN_COLS < n ? xa + OWN_COLS : n;
+    const int64_t nwords = (n + 63) >> 6;
+    const int64_t w0 = xa - U > 0 ? ((xa - U) >> 6) : 0;
+    const int64_t w1 = (xb + 63) >> 6;
+    if (w1 - w0 > WAVE || U + TS::TR + 1 >= (1 << HB)) return false;  // heights and tested k fit
+    const int64_t wl = w0 + lane;
+    const bool valid = wl < w1;
+    const int64_t wl_c = valid ? wl : w0;
+    const uint64_t wmask = !valid ? 0ull : (wl == nwords - 1 ? last_word_mask(n) : ~0ull);
+    uint64_t own = 0;
+    if (valid) {
+        const int64_t lo = (xa > wl * 64 ? xa : wl * 64) - wl * 64;
+        const int64_t hi = (xb < wl * 64 + 64 ? xb : wl * 64 + 64) - wl * 64;
+        if (hi > lo) own = (hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1)) << lo;
+    }
+    // heights at row ra - 1, at most U rows deep
+    uint64_t P[HB];
+#pragma unroll
+    for (int p = 0; p < HB; ++p) P[p] = 0;
+    uint64_t acc = valid ? ~0ull : 0ull;
+    const int64_t rstop = ra - U > 0 ? ra - U : 0;
+    constexpr int FB = 16;  // rows loaded per round (all in flight together)
+    for (int64_t r0 = ra - 1; r0 >= rstop; r0 -= FB) {
+        uint64_t v[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const int64_t r = r0 - u >= rstop ? r0 - u : rstop;  // clamped: the loads batch
+            v[u] = bits[r * ldw + wl_c];
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            if (r0 - u < rstop) break;
+            acc &= v[u] & wmask;
+            planes_inc_masked(P, acc);
+        }
+        if (!__ballot(acc != 0)) break;
+    }
+    // the tile's rows, FB at a time
+    int32_t best = 0;
+    int64_t bpos = 0;
+    for (int64_t i0 = ra; i0 < rb; i0 += FB) {
+        uint64_t v[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const int64_t r = i0 + u < rb ? i0 + u : rb - 1;
+            v[u] = bits[r * ldw + wl_c];
+        }
+        for (int u = 0; u < FB; ++u) {
+            const int64_t i = i0 + u;
+            if (i >= rb) break;
+            const uint64_t x = v[u] & wmask;
+            planes_inc_masked(P, ~0ull);
+#pragma unroll
+            for (int p = 0; p < HB; ++p) P[p] &= x;
+            int64_t col = 0;
+            if (i == ra) {
+                int32_t lo = 0, k = 1;
+                int64_t lo_col = 0;
+                while (k <= U + TS::TR && row_test(P, k, own, lane, w0, &col)) {
+                    lo = k;
+                    lo_col = col;
+                    k <<= 1;
+                }
+                int32_t hi = k < U + TS::TR + 1 ? k : (int32_t)(U + TS::TR + 1);
+                while (hi - lo > 1) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (row_test(P, mid, own, lane, w0, &col)) {
+                        lo = mid;
+                        lo_col = col;
+                    } else {
+                        hi = mid;
+                    }
+                }
+                best = lo;
+                bpos = i * n + lo_col;
+            } else if (row_test(P, best + 1, own, lane, w0, &col)) {
+                ++best;
+                bpos = i * n + col;
+            }
+        }
+    }
+    *best_out = best;
+    *bpos_out = bpos;
+    return true;
+}
+
+template <class TS>
+__device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
+                             int64_t ldw, int64_t ty, int64_t tx, int64_t ntx,
+                             const uint8_t *__restrict__ sat, unsigned long long *key,
+                             uint32_t *serial_flag) {
+    constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
+    const int lane = __lane_id();
+    m = uniform(m);
+    n = uniform(n);
+    ldw = uniform(ldw);
+    ty = uniform(ty);
+    tx = uniform(tx);
+    const int64_t vrun = uniform(sat_run(sat, ty * ntx + tx, ntx, ty + 1, lane));
+    const int64_t hrun = uniform(sat_run(sat, ty * ntx + tx, 1, tx + 1, lane));
+    int64_t ucap = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
+    const int64_t mn = m < n ? m : n;
+    ucap = ucap < mn ? ucap : mn;
+    const int64_t g = uniform(key_side(load_relaxed(key)));
+    if (ucap < g) return;  // cannot reach the best side found so far
+    // one pass at the bound when its window fits (exact at once), else doubling from twice
+    // the best side so far (the bound is loose where most tiles saturate)
+    const int64_t w0cap = tx * OWN_COLS - ucap > 0 ? ((tx * OWN_COLS - ucap) >> 6) : 0;
+    const int64_t w1cap = ((tx + 1) * OWN_COLS < n ? (tx + 1) * OWN_COLS + 63 : n + 63) >> 6;
+    const bool cap_fits = w1cap - w0cap <= WAVE && ucap + TS::TR + 1 < (1 << HB);
+    int64_t U = cap_fits ? ucap : 2 * (g > TS::KC ? g : TS::KC);
+    for (;;) {
+        U = U < ucap ? U : ucap;
+        int32_t best = 0;
+        int64_t bpos = 0;
+        if (!resolve_pass<TS>(bits, m, n, ldw, ty, tx, U, &best, &bpos)) {
+            if (lane == 0) atomicOr(serial_flag, 1u);  // the serial pass finishes the matrix
+            return;
+        }
+        best = uniform(best);
+        if (best < U || U >= ucap) {
+            if (lane == 0 && best > 0) atomicMax(key, make_key(best, bpos));
+            return;
+        }
+        U = 2 * (int64_t)best;
     }
 }
 

@@ -2,14 +2,17 @@
 //
 // Single matrix, largest square (two launches):
 //   k_probe    : erosion search over register tiles (device.hpp tile_search).  Each tile pushes
-//                its exact side with its first corner into one atomic key; a tile holding a
-//                square beyond its certified side runs the windowed dp pass on its own cells.
-//   k_finalize : one wave turns the key into the result (or, for a square too wide for any
-//                window, runs the serial pass) and clears the scratch for the next call.
+//                its exact side (up to the side its halo certifies) with its first corner into
+//                one atomic key, and writes a saturation byte: 1 when it holds a larger square.
+//   k_resolve  : if any tile saturated, finishes those tiles exactly with column heights and a
+//                per-row test (device.hpp resolve_tile); the last wave to finish (or, with no
+//                saturated tile, the first wave) turns the key into the result (running the
+//                serial pass for a square too wide for the resolve pass) and clears the scratch.
 // dp map (one more launch): k_dpmap reads S on the device and covers the matrix with row bands
 // and column windows that start S rows / columns early (zero state there is exact).
 // Batched: k_batch_init (prefix of tile counts, clear keys), k_probe_batched (every tile of every
-// matrix in one grid-stride pass), k_batch_final (key -> result per matrix).
+// matrix in one grid-stride pass), k_batch_resolve (saturated tiles of every matrix),
+// k_batch_final (key -> result per matrix).
 #include <algorithm>
 
 #include "device.hpp"
@@ -91,17 +94,18 @@ __global__ __launch_bounds__(256) void k_pack_u8(const uint8_t *__restrict__ a, 
 template <class TS>
 __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits, int64_t m,
                                                int64_t n, int64_t ldw, int64_t ntiles,
-                                               int64_t ntx, mshost::ScratchHeader *hdr) {
-    __shared__ uint64_t lx[4][LDS_WORDS];
-    __shared__ int32_t lc[4][LDS_WORDS];
-    const int wib = threadIdx.x / WAVE;
-    const TileSink sink{&hdr->key, &hdr->serial_flag, WaveLds{lx[wib], lc[wib]}};
+                                               int64_t ntx, mshost::ScratchHeader *hdr,
+                                               uint8_t *__restrict__ sat) {
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    SatBatch sb{sat};
+    sb.stride = nwave;
     for (int64_t t = wave; t < ntiles; t += nwave) {
         const int64_t ty = t / ntx, tx = t - ty * ntx;
-        tile_search<TS>(bits, m, n, ldw, ty, tx, sink);
+        sb.add(t, tile_search<TS>(bits, m, n, ldw, ty, tx, TileSink{&hdr->key}));
     }
+    sb.flush();
+    if (__lane_id() == 0 && sb.nsat) atomicAdd(&hdr->nsat, (uint32_t)sb.nsat);
 }
 
 __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) {
@@ -118,12 +122,11 @@ __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) 
     *dst = r;
 }
 
-// One wave: key -> result (serial pass if a square was too wide for the windowed pass), then
-// clear the scratch.
-__global__ __launch_bounds__(64) void k_finalize(const uint64_t *__restrict__ bits, int64_t m,
-                                                 int64_t n, int64_t ldw,
-                                                 mshost::ScratchHeader *hdr,
-                                                 int32_t *serial_state, ms_square *out) {
+// One wave: key -> result (serial pass if a square was too wide for the resolve pass), then
+// clear the header for the next call.
+__device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
+                              int64_t ldw, mshost::ScratchHeader *hdr, int32_t *serial_state,
+                              ms_square *out) {
     const int lane = __lane_id();
     // both loads in flight together (device-scope: written by other waves' atomics)
     unsigned long long key = load_relaxed(&hdr->key);
@@ -140,6 +143,48 @@ __global__ __launch_bounds__(64) void k_finalize(const uint64_t *__restrict__ bi
         if (out) write_result(key, n, out);
         hdr->key = 0;
         hdr->serial_flag = 0;
+        hdr->nsat = 0;
+        hdr->done = 0;
+    }
+}
+
+// After the probe: if any tile saturated, finish those tiles exactly (resolve_tile), spread over
+// the waves so that clustered saturated tiles land on different waves; the last wave to finish
+// (a completion count, no waiting) writes the result.  With no saturated tile, the first wave
+// writes it at once and every other wave returns.
+template <class TS>
+__global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bits, int64_t m,
+                                                 int64_t n, int64_t ldw, int64_t ntiles,
+                                                 int64_t ntx, mshost::ScratchHeader *hdr,
+                                                 const uint8_t *__restrict__ sat,
+                                                 int32_t *serial_state, ms_square *out) {
+    const int lane = __lane_id();
+    const int64_t wave = wave_index();
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const uint32_t nsat = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->nsat));
+    if (nsat == 0) {
+        if (wave == 0) finalize_wave(bits, m, n, ldw, hdr, serial_state, out);
+        return;
+    }
+    // tiles wave, wave + nwave, ...: 64 saturation bytes per round
+    for (int64_t base = wave; base < ntiles; base += 64 * nwave) {
+        const int64_t t = base + (int64_t)lane * nwave;
+        uint64_t b = __ballot(t < ntiles && sat[t] != 0);
+        while (b) {
+            const int l = __ffsll((long long)b) - 1;
+            b &= b - 1;
+            const int64_t tt = base + (int64_t)l * nwave;
+            const int64_t ty = tt / ntx, tx = tt - ty * ntx;
+            resolve_tile<TS>(bits, m, n, ldw, ty, tx, ntx, sat, &hdr->key, &hdr->serial_flag);
+        }
+    }
+    __threadfence();
+    uint32_t prev = 0;
+    if (lane == 0) prev = atomicAdd(&hdr->done, 1u);
+    prev = (uint32_t)__shfl((int32_t)prev, 0);
+    if (prev == (uint32_t)(nwave - 1)) {
+        __threadfence();
+        finalize_wave(bits, m, n, ldw, hdr, serial_state, out);
     }
 }
 
@@ -209,7 +254,8 @@ __global__ void k_write_result(ms_square *out, mshost::ScratchHeader *hdr, int64
 // ---------------------------------------------------------------------------------- batched
 struct BatchCounters {
     uint32_t error;   // bit 1: the device prefix disagrees with the host's tile count
-    uint32_t pad[7];
+    uint32_t nsat;    // saturated tiles over the whole batch
+    uint32_t pad[6];
 };
 
 // One block: clear per-matrix keys and flags, exclusive prefix of tile counts.
@@ -254,6 +300,7 @@ __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict
     if (tid == 1023) {
         prefix[count] = part[1023];
         ctr->error = 0;
+        ctr->nsat = 0;
     }
 }
 
@@ -276,17 +323,16 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
                                                        int64_t count,
                                                        unsigned long long *__restrict__ keys,
                                                        const uint64_t *__restrict__ prefix,
-                                                       uint32_t *__restrict__ flags,
-                                                       BatchCounters *ctr, uint64_t total) {
-    __shared__ uint64_t lx[4][LDS_WORDS];
-    __shared__ int32_t lc[4][LDS_WORDS];
-    const int wib = threadIdx.x / WAVE;
+                                                       BatchCounters *ctr,
+                                                       uint8_t *__restrict__ sat, uint64_t total) {
     if (__hip_atomic_load(prefix + count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != total) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->error, 2u);
         return;
     }
     const uint64_t wave = (uint64_t)wave_index();
     const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+    SatBatch sb{sat};
+    sb.stride = (int64_t)nwave;
     for (uint64_t item = wave; item < total; item += nwave) {
         const int64_t mi = find_matrix(prefix, count, item);
         const ms_matrix d = mats[mi];
@@ -294,8 +340,44 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
         const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
         const int64_t t = (int64_t)(item - prefix[mi]);
         const int64_t ty = t / ntx, tx = t - ty * ntx;
-        const TileSink sink{keys + mi, flags + mi, WaveLds{lx[wib], lc[wib]}};
-        tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, sink);
+        sb.add((int64_t)item,
+               tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, TileSink{keys + mi}));
+    }
+    sb.flush();
+    if (__lane_id() == 0 && sb.nsat) atomicAdd(&ctr->nsat, (uint32_t)sb.nsat);
+}
+
+// Saturated tiles of every matrix (none: every wave returns at once), spread over the waves.
+template <class TS>
+__global__ __launch_bounds__(256) void k_batch_resolve(const ms_matrix *__restrict__ mats,
+                                                       int64_t count,
+                                                       unsigned long long *__restrict__ keys,
+                                                       const uint64_t *__restrict__ prefix,
+                                                       uint32_t *__restrict__ flags,
+                                                       const BatchCounters *ctr,
+                                                       const uint8_t *__restrict__ sat,
+                                                       uint64_t total) {
+    const int lane = __lane_id();
+    if (uniform((int32_t)load_relaxed_u32(&ctr->nsat)) == 0) return;
+    if (load_relaxed_u32(&ctr->error)) return;
+    const uint64_t wave = (uint64_t)wave_index();
+    const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+    for (uint64_t base = wave; base < total; base += 64 * nwave) {
+        const uint64_t g = base + (uint64_t)lane * nwave;
+        uint64_t b = __ballot(g < total && sat[g] != 0);
+        while (b) {
+            const int l = __ffsll((long long)b) - 1;
+            b &= b - 1;
+            const uint64_t item = base + (uint64_t)l * nwave;
+            const int64_t mi = find_matrix(prefix, count, item);
+            const ms_matrix d = mats[mi];
+            const int64_t nwords = (d.n + 63) >> 6;
+            const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
+            const int64_t t = (int64_t)(item - prefix[mi]);
+            const int64_t ty = t / ntx, tx = t - ty * ntx;
+            resolve_tile<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
+                             keys + mi, flags + mi);
+        }
     }
 }
 
@@ -368,30 +450,38 @@ hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int
 }
 
 template <class TS>
-static hipError_t launch_probe(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
-                               int64_t ldw, ScratchHeader *hdr) {
+static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits, int64_t m,
+                                      int64_t n, int64_t ldw, ScratchHeader *hdr,
+                                      int32_t *serial_state, uint8_t *sat, ms_square *out) {
     const int64_t ntx = cdiv(cdiv(n, 64), TS::OWN_WORDS);
     const int64_t ntiles = cdiv(m, TS::TR) * ntx;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 4),
                                                                    (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_probe<TS>, dim3((unsigned)blocks), dim3(256), 0, env.stream, bits,
-                       m, n, ldw, ntiles, ntx, hdr);
+                       m, n, ldw, ntiles, ntx, hdr, sat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t rblocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 8),
+                                                                    (int64_t)env.num_cus * 2));
+    hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks), dim3(256), 0, env.stream,
+                       bits, m, n, ldw, ntiles, ntx, hdr, sat, serial_state, out);
     return hipGetLastError();
+}
+
+int64_t max_probe_tiles(int64_t m, int64_t n) {
+    const int64_t nw = cdiv(std::max<int64_t>(n, 1), 64);
+    const int64_t rows = std::min<int64_t>({TS0::TR, TS1::TR, TS2::TR});
+    return cdiv(std::max<int64_t>(m, 1), rows) * cdiv(nw, (int64_t)PROBE_TILE_WORDS);
 }
 
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             ms_square *out) {
-    hipError_t e;
+                             uint8_t *sat, ms_square *out) {
     switch (variant) {
-    case 0: e = launch_probe<TS0>(env, bits, m, n, ldw, hdr); break;
-    case 1: e = launch_probe<TS1>(env, bits, m, n, ldw, hdr); break;
-    default: e = launch_probe<TS2>(env, bits, m, n, ldw, hdr); break;
+    case 0: return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, out);
+    case 1: return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, out);
+    default: return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, out);
     }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(msk::k_finalize, dim3(1), dim3(64), 0, env.stream, bits, m, n, ldw, hdr,
-                       serial_state, out);
-    return hipGetLastError();
 }
 
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
@@ -461,6 +551,7 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
     L.prefix = off; off = align256(off + sizeof(uint64_t) * (size_t)(count + 1));
     L.flags = off; off = align256(off + sizeof(uint32_t) * (size_t)count);
     L.serial_state = off; off = align256(off + sizeof(int32_t) * 2 * 64 * (size_t)maxw);
+    L.sat = off; off = align256(off + (size_t)tiles);
     L.total = off;
     return L;
 }
@@ -473,6 +564,7 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     auto *prefix = reinterpret_cast<uint64_t *>(ws + L.prefix);
     auto *flags = reinterpret_cast<uint32_t *>(ws + L.flags);
     auto *state = reinterpret_cast<int32_t *>(ws + L.serial_state);
+    auto *sat = reinterpret_cast<uint8_t *>(ws + L.sat);
     hipLaunchKernelGGL(msk::k_batch_init<TS>, dim3(1), dim3(1024), 0, env.stream, mats, count,
                        keys, prefix, flags, ctr);
     hipError_t e = hipGetLastError();
@@ -480,7 +572,12 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     const int64_t pblocks = std::max<int64_t>(
         1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 4), (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)pblocks), dim3(256), 0,
-                       env.stream, mats, count, keys, prefix, flags, ctr,
+                       env.stream, mats, count, keys, prefix, ctr, sat, (uint64_t)L.total_tiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t rblocks = std::max<int64_t>(
+        1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 8), (int64_t)env.num_cus * 2));
+    hipLaunchKernelGGL(msk::k_batch_resolve<TS>, dim3((unsigned)rblocks), dim3(256), 0,
+                       env.stream, mats, count, keys, prefix, flags, ctr, sat,
                        (uint64_t)L.total_tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t fb = std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)env.num_cus * 4));

@@ -13,10 +13,12 @@ namespace mshost {
 // end of every call, so the scratch needs clearing only once, when it is allocated.
 struct ScratchHeader {
     unsigned long long key;     // running best (side, position) key
-    uint32_t serial_flag;       // a square was too wide for the windowed exact pass
-    uint32_t pad0;
+    uint32_t serial_flag;       // a square was too wide for the resolve pass
+    uint32_t nsat;              // saturated tiles found by the probe
     ms_square result;           // last result (read by the map pass)
-    uint64_t pad1[3];
+    uint32_t done;              // waves of the resolve pass that have finished
+    uint32_t pad0;
+    uint64_t pad1[2];
 };
 static_assert(sizeof(ScratchHeader) == 64, "header layout");
 
@@ -39,10 +41,12 @@ struct LaunchEnv {
 hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int64_t n,
                           int64_t ldb, uint64_t *bits, int64_t ldw);
 
-// Largest square of one matrix; result into hdr->result and, if non-null, *out.
+// Largest square of one matrix; result into hdr->result and, if non-null, *out.  `sat` holds
+// one byte per probe tile (max_probe_tiles(m, n) bytes cover every variant).
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             ms_square *out);
+                             uint8_t *sat, ms_square *out);
+int64_t max_probe_tiles(int64_t m, int64_t n);
 
 // dp map of one matrix; reads S from *maxsq on the device (a largest-square result).
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
@@ -55,7 +59,7 @@ hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHead
 
 // Batched: workspace layout and launches.
 struct BatchLayout {
-    size_t keys, prefix, counters, serial_state, flags, total;
+    size_t keys, prefix, counters, serial_state, flags, sat, total;
     uint64_t total_tiles;
     int64_t max_nwords;
 };

@@ -164,3 +164,51 @@ def test_repeated_calls_reuse_scratch(dev):
         for d, n, ref in ds:
             sq = M.max_square(d, n)
             assert (sq.side, sq.row, sq.col) == ref
+
+
+@pytest.mark.parametrize("where", ["top_left", "bottom_right", "tile_seams", "far_right"])
+@pytest.mark.parametrize("side", [40, 130, 1000])
+def test_saturated_tiles_at_edges(dev, where, side):
+    """Squares beyond the tiles' certified side, placed against the matrix borders (column
+    heights reaching row 0, windows clipped at column 0 and at n) and across tile seams."""
+    announce("saturated", where, side)
+    rng = np.random.default_rng([side, len(where)])
+    m, n = (1200, 7000) if where == "far_right" else (1300, 2100)
+    a = (rng.random((m, n)) < 0.7).astype(np.uint8)
+    if where == "top_left":
+        r0, c0 = 0, 0
+    elif where == "bottom_right":
+        r0, c0 = m - side, n - side
+    elif where == "tile_seams":
+        r0, c0 = max(0, 113 * 3 - side // 2), max(0, 960 - side // 2)
+    else:
+        r0, c0 = 100, n - side - 3
+    a[r0:r0 + side, c0:c0 + side] = 1
+    assert_same(a, dev)
+
+
+@pytest.mark.parametrize("layout", ["same_row", "earlier_row_later_col", "touching"])
+def test_equal_squares_first_corner(dev, layout):
+    """Several squares of the maximal side: the reported corner is the first bottom-right
+    corner in row-major order."""
+    announce("ties", layout)
+    rng = np.random.default_rng(len(layout))
+    m, n = 900, 2500
+    a = (rng.random((m, n)) < 0.5).astype(np.uint8)
+    s = 60
+    if layout == "same_row":
+        spots = [(300, 1800), (300, 200), (300, 1000)]
+    elif layout == "earlier_row_later_col":
+        spots = [(500, 100), (200, 2300), (350, 1200)]
+    else:
+        spots = [(100, 100), (100, 100 + s), (100 + s, 100)]
+    for r0, c0 in spots:
+        a[r0:r0 + s, c0:c0 + s] = 1
+    assert_same(a, dev)
+
+
+def test_resolve_falls_back_to_serial(dev):
+    """A square so wide that the column-height window exceeds one word per lane: the serial
+    pass finishes the matrix."""
+    announce("serial fallback 3300")
+    assert_same(np.ones((3300, 3300), np.uint8), dev)
