@@ -129,11 +129,15 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
 
 /*
  * Many matrices in one go.  h_mats is a host copy of the `count` descriptors whose device
- * copy is d_mats; results go to d_out[0 .. count-1] in the same order.  The work of all
- * matrices is spread over one persistent launch pulling (matrix, tile) items from a device
- * queue; the launch sequence is recorded once into a HIP graph and replayed afterwards.
+ * copy is d_mats; results go to d_out[0 .. count-1] in the same order.  The tiles of all
+ * matrices are spread over one grid-stride launch (the tile total is computed on the host from
+ * h_mats and checked on the device against a prefix of d_mats' tile counts; a mismatch turns
+ * every result into side -1 instead of running).  With the environment variable MAXSQ_GRAPH=1
+ * the launch sequence is captured once per (descriptors, shapes, output, workspace) into a HIP
+ * graph and replayed on later calls.
  * The caller provides the workspace (size from ms_batched_workspace_size with the same
- * descriptors); the library keeps no pointer to it after the work completes.
+ * descriptors; that size fits every probe variant); the library keeps no pointer to it after
+ * the work completes.
  * Invalid: count < 0; any descriptor invalid as in ms_max_square; NULL pointers with
  * count > 0.  MS_ERR_WORKSPACE_TOO_SMALL if workspace_bytes is below the required size.
  */
@@ -155,6 +159,12 @@ ms_status ms_set_config(ms_ctx *ctx, const ms_config *cfg);
 ms_status ms_get_config(ms_ctx *ctx, int64_t m, int64_t n, ms_config *cfg);
 ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                       int64_t ld_words, int32_t *d_dp_scratch, int64_t ld_dp, void *stream);
+/* ms_autotune_batched times every probe variant on the caller's batch (same arguments as
+ * ms_max_square_batched, whose results it leaves in d_out; blocking) and records the fastest
+ * for later batched calls on this context. */
+ms_status ms_autotune_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_matrix *d_mats,
+                              int64_t count, ms_square *d_out, void *d_workspace,
+                              size_t workspace_bytes, void *stream);
 ms_status ms_autotune_save(ms_ctx *ctx, const char *path);
 ms_status ms_autotune_load(ms_ctx *ctx, const char *path);
 

@@ -97,6 +97,7 @@ def lib():
             "ms_set_config": [_P, ctypes.POINTER(_Config)],
             "ms_get_config": [_P, _I64, _I64, ctypes.POINTER(_Config)],
             "ms_autotune": [_P, _P, _I64, _I64, _I64, _P, _I64, _P],
+            "ms_autotune_batched": [_P, _P, _P, _I64, _P, _P, ctypes.c_size_t, _P],
             "ms_autotune_save": [_P, ctypes.c_char_p],
             "ms_autotune_load": [_P, ctypes.c_char_p],
         }
@@ -184,6 +185,11 @@ def ms_get_config(ctx, m: int, n: int) -> dict:
 
 def ms_autotune(ctx, d_bits, m, n, ld_words, d_dp, ld_dp, stream) -> None:
     _check(lib().ms_autotune(ctx, d_bits, m, n, ld_words, d_dp, ld_dp, stream), "ms_autotune")
+
+
+def ms_autotune_batched(ctx, h_mats, d_mats, count, d_out, d_ws, ws_bytes, stream) -> None:
+    _check(lib().ms_autotune_batched(ctx, h_mats, d_mats, count, d_out, d_ws, ws_bytes, stream),
+           "ms_autotune_batched")
 
 
 def ms_autotune_save(ctx, path: str) -> None:
@@ -344,6 +350,14 @@ class Batch:
         _check(ms_max_square_batched(self.ctx, self.h_mats, self.d_mats.data_ptr(), self.count,
                                      self.out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
                                      _stream(stream)), "ms_max_square_batched")
+        return self.out[: self.count]
+
+    def autotune(self, stream=None):
+        """Time every probe variant on this batch; later runs on the same context use the
+        fastest (the results of this call are left in `out`)."""
+        ms_autotune_batched(self.ctx, self.h_mats, self.d_mats.data_ptr(), self.count,
+                            self.out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                            _stream(stream))
         return self.out[: self.count]
 
     def results(self):

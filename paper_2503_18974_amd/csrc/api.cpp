@@ -67,6 +67,7 @@ struct ms_ctx {
     bool dirty = false;
     bool has_forced = false;
     ms_config forced{};
+    int batched_variant = -1;  // from ms_autotune_batched (or a loaded table); -1: default
     std::map<int, ms_config> tuned;
     std::vector<GraphEntry> graphs;
     hipStream_t capture_stream = nullptr;
@@ -360,9 +361,11 @@ ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_
         if (s != MS_OK) return s;
     }
     if (count >= (int64_t(1) << 24)) return MS_ERR_INVALID_ARGUMENT;
-    int variant = DEFAULT_CONFIG.probe_variant;
-    if (ctx && ctx->has_forced) variant = ctx->forced.probe_variant;
-    *bytes = mshost::batch_layout(variant, h_mats, count).total;
+    (void)ctx;
+    size_t need = 0;  // enough for every variant, so a tuned choice always fits
+    for (int v = 0; v < mshost::NUM_PROBE_VARIANTS; ++v)
+        need = std::max(need, mshost::batch_layout(v, h_mats, count).total);
+    *bytes = need;
     return MS_OK;
 }
 
@@ -381,7 +384,9 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
     ms_status s = resolve(ctx, &c);
     if (s != MS_OK) return s;
     std::lock_guard<std::mutex> lk(c->mu);
-    const int variant = c->has_forced ? c->forced.probe_variant : DEFAULT_CONFIG.probe_variant;
+    const int variant = c->has_forced ? c->forced.probe_variant
+                        : c->batched_variant >= 0 ? c->batched_variant
+                                                  : DEFAULT_CONFIG.probe_variant;
     const mshost::BatchLayout L = mshost::batch_layout(variant, h_mats, count);
     if (workspace_bytes < L.total) return MS_ERR_WORKSPACE_TOO_SMALL;
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
@@ -534,12 +539,72 @@ ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
     return s;
 }
 
+ms_status ms_autotune_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_matrix *d_mats,
+                              int64_t count, ms_square *d_out, void *d_workspace,
+                              size_t workspace_bytes, void *stream) {
+    if (count <= 0 || !h_mats || !d_mats || !d_out || !d_workspace) return MS_ERR_INVALID_ARGUMENT;
+    if (count >= (int64_t(1) << 24)) return MS_ERR_INVALID_ARGUMENT;
+    for (int64_t i = 0; i < count; ++i) {
+        ms_status s = validate_packed(h_mats[i].bits, h_mats[i].m, h_mats[i].n, h_mats[i].ld_words);
+        if (s != MS_OK) return s;
+    }
+    ms_ctx *c = nullptr;
+    ms_status s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MS_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MS_ERR_HIP;
+    }
+    mshost::LaunchEnv env{c->num_cus, st};
+    int best_v = DEFAULT_CONFIG.probe_variant;
+    float best_t = 1e30f;
+    for (int v = 0; v < mshost::NUM_PROBE_VARIANTS && s == MS_OK; ++v) {
+        const mshost::BatchLayout L = mshost::batch_layout(v, h_mats, count);
+        if (workspace_bytes < L.total) {
+            s = MS_ERR_WORKSPACE_TOO_SMALL;
+            break;
+        }
+        const int reps = 3;
+        hipError_t e = mshost::launch_batched(env, v, d_mats, count, d_out, d_workspace, L);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = mshost::launch_batched(env, v, d_mats, count, d_out, d_workspace, L);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            s = hip_status(e);
+            break;
+        }
+        if (ms < best_t) {
+            best_t = ms;
+            best_v = v;
+        }
+    }
+    // leave the results of the chosen variant in d_out
+    if (s == MS_OK) {
+        const mshost::BatchLayout L = mshost::batch_layout(best_v, h_mats, count);
+        s = hip_status(mshost::launch_batched(env, best_v, d_mats, count, d_out, d_workspace, L));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s == MS_OK) c->batched_variant = best_v;
+    return s;
+}
+
 ms_status ms_autotune_save(ms_ctx *ctx, const char *path) {
     if (!ctx || !path) return MS_ERR_INVALID_ARGUMENT;
     std::lock_guard<std::mutex> lk(ctx->mu);
     FILE *f = std::fopen(path, "w");
     if (!f) return MS_ERR_INVALID_ARGUMENT;
     std::fprintf(f, "# maxsq autotune table: bucket probe_variant map_cols map_band_rows\n");
+    if (ctx->batched_variant >= 0) std::fprintf(f, "batched %d\n", ctx->batched_variant);
     for (auto &kv : ctx->tuned)
         std::fprintf(f, "%d %d %d %d\n", kv.first, kv.second.probe_variant, kv.second.map_cols,
                      kv.second.map_band_rows);
@@ -552,10 +617,20 @@ ms_status ms_autotune_load(ms_ctx *ctx, const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return MS_ERR_INVALID_ARGUMENT;
     std::map<int, ms_config> table;
+    int batched = -1;
     char line[256];
     ms_status s = MS_OK;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
+        int bv = -1;
+        if (std::sscanf(line, "batched %d", &bv) == 1) {
+            if (bv < 0 || bv >= mshost::NUM_PROBE_VARIANTS) {
+                s = MS_ERR_INVALID_ARGUMENT;
+                break;
+            }
+            batched = bv;
+            continue;
+        }
         int b = 0;
         ms_config cfg{};
         if (std::sscanf(line, "%d %d %d %d", &b, &cfg.probe_variant, &cfg.map_cols,
@@ -569,6 +644,7 @@ ms_status ms_autotune_load(ms_ctx *ctx, const char *path) {
     if (s != MS_OK) return s;
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &kv : table) ctx->tuned[kv.first] = kv.second;
+    if (batched >= 0) ctx->batched_variant = batched;
     return MS_OK;
 }
 

@@ -51,42 +51,43 @@ __device__ __forceinline__ uint4 load16(const uint8_t *__restrict__ p) {
     }
 }
 
-// One packed word (64 columns) per thread: four 16-byte loads in flight, one 8-byte store.
-// Row starts are ALIGN-byte aligned (ALIGN divides both the base address and ld_bytes).
+// One 16-byte chunk per lane, so a wave's loads cover 1 KB of a row contiguously; the four lanes
+// of a quad hold the four chunks of one packed word and merge their 16-bit masks with two DPP
+// quad permutes, and the quad's first lane stores the word.  Chunks past n (the row's padding)
+// give zero bits.  Row starts are ALIGN-byte aligned (ALIGN divides the base and ld_bytes).
 template <int ALIGN>
 __global__ __launch_bounds__(256) void k_pack_u8(const uint8_t *__restrict__ a, int64_t m,
                                                  int64_t n, int64_t ldb,
                                                  uint64_t *__restrict__ bits, int64_t ldw) {
-    const int64_t nwords = (n + 63) >> 6;
-    const int64_t total = m * nwords;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int64_t row, w;
+    const int64_t cpr = ((n + 63) >> 6) * 4;  // 16-byte chunks per packed row
+    const int64_t total = m * cpr;            // a multiple of 4, as is the stride below
+    const int q = __lane_id() & 3;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        int64_t row, c;
         if (total <= 0xFFFFFFFFll) {
-            row = (uint32_t)t / (uint32_t)nwords;
-            w = (uint32_t)t - (uint32_t)row * (uint32_t)nwords;
+            row = (uint32_t)t / (uint32_t)cpr;
+            c = (uint32_t)t - (uint32_t)row * (uint32_t)cpr;
         } else {
-            row = t / nwords;
-            w = t - row * nwords;
+            row = t / cpr;
+            c = t - row * cpr;
         }
-        const uint8_t *__restrict__ src = a + row * ldb + w * 64;
-        uint64_t word = 0;
-        if ((w + 1) * 64 <= n) {
-            uint4 v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = load16<ALIGN>(src + 16 * k);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t m16 = nz4(v[k].x) | (nz4(v[k].y) << 4) | (nz4(v[k].z) << 8) |
-                                     (nz4(v[k].w) << 12);
-                word |= (uint64_t)m16 << (16 * k);
-            }
-        } else {
-            const int64_t rem = n - w * 64;
-            for (int64_t k = 0; k < rem; ++k)
-                if (src[k] != 0) word |= 1ull << k;
+        const int64_t off = c * 16;
+        const uint8_t *__restrict__ src = a + row * ldb + off;
+        uint32_t m16 = 0;
+        if (off + 16 <= n) {
+            const uint4 v = load16<ALIGN>(src);
+            m16 = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+        } else if (off < n) {
+            for (int64_t k = 0; k < n - off; ++k)
+                if (src[k] != 0) m16 |= 1u << k;
         }
-        bits[row * ldw + w] = word;
+        // quad_perm [1,0,3,2]: lanes 0 and 2 of the quad receive lanes 1 and 3
+        const uint32_t pair = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)m16, 0xB1, 0xf, 0xf, false);
+        const uint32_t half = m16 | (pair << 16);
+        // quad_perm [2,3,0,1]: lane 0 receives lane 2's upper half
+        const uint32_t upper = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)half, 0x4E, 0xf, 0xf, false);
+        if (q == 0) bits[row * ldw + (c >> 2)] = ((uint64_t)upper << 32) | half;
     }
 }
 
@@ -437,8 +438,8 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int64_t n,
                           int64_t ldb, uint64_t *bits, int64_t ldw) {
-    const int64_t words = m * cdiv(n, 64);
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(words, 256),
+    const int64_t chunks = m * cdiv(n, 64) * 4;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(chunks, 256),
                                                                    (int64_t)env.num_cus * 32));
     const uintptr_t al = (uintptr_t)a | (uintptr_t)ldb;
     const dim3 g((unsigned)blocks), b(256);
