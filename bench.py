@@ -305,8 +305,10 @@ def serve_section(dev, rates, count, pool_size, budget_gib):
         s = st.summary()
         s["rate_req_s"] = rate
         s["offered_gcells_s"] = rate * mean_cells / 1e9
-        log("serve %s %d req/s: p50 %.2f ms, p99 %.2f ms, %.1f Gcells/s, mean batch %.1f"
-            % (tag, rate, s["p50_ms"], s["p99_ms"], s["gcells_s"], s["mean_batch"]))
+        log("serve %s %d req/s: p50 %.2f ms, p99 %.2f ms (p99 queue %.2f, launch wait %.2f, "
+            "device %.2f), %.1f Gcells/s, mean batch %.1f"
+            % (tag, rate, s["p50_ms"], s["p99_ms"], s["p99_queue_ms"], s["p99_launch_wait_ms"],
+               s["p99_device_ms"], s["gcells_s"], s["mean_batch"]))
         return s
 
     out = {"pool": pool_size, "mean_cells": mean_cells, "budget_bytes": budget,

@@ -24,6 +24,7 @@ from __future__ import annotations
 import bisect
 import collections
 import ctypes
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -136,10 +137,11 @@ class WallClock:
         return time.perf_counter() - self.t0
 
     def wait(self, until: float) -> None:
-        """Idle until `until` (seconds) at most; short waits spin, longer ones sleep."""
+        """Idle until `until` (seconds) at most: waits under a millisecond spin (a sleep can
+        overshoot by much more than that), longer ones sleep to half a millisecond before."""
         dt = until - self.now()
-        if dt > 2e-4:
-            time.sleep(dt - 1e-4)
+        if dt > 1e-3:
+            time.sleep(dt - 5e-4)
 
 
 @dataclass
@@ -152,6 +154,9 @@ class Stats:
     max_queue: int = 0
     peak_bytes: int = 0
     latencies: list = field(default_factory=list)
+    queue_waits: list = field(default_factory=list)    # arrival -> admitted
+    launch_waits: list = field(default_factory=list)   # admitted -> launched
+    device_times: list = field(default_factory=list)   # launched -> result seen
     first_arrival: float = 0.0
     last_done: float = 0.0
     batch_sizes: list = field(default_factory=list)
@@ -159,7 +164,13 @@ class Stats:
     def summary(self) -> dict:
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
         span = max(self.last_done - self.first_arrival, 1e-9)
+
+        def p99(v):
+            return float(np.percentile(np.array(v), 99) * 1e3) if v else 0.0
+
         return {
+            "p99_queue_ms": p99(self.queue_waits), "p99_launch_wait_ms": p99(self.launch_waits),
+            "p99_device_ms": p99(self.device_times),
             "requests": self.requests, "completed": self.completed, "rejected": self.rejected,
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -186,6 +197,17 @@ class Server:
         self.on_complete = on_complete
 
     def run(self, requests) -> Stats:
+        """Serve `requests` (arrival times relative to the start of this call); the collector
+        is paused meanwhile so that its pauses do not land in the latencies."""
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests)
+        finally:
+            if was_enabled:
+                gc.enable()
+
+    def _run(self, requests) -> Stats:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         st = Stats(requests=len(reqs))
         st.first_arrival = reqs[0].arrival if reqs else 0.0
@@ -217,6 +239,9 @@ class Server:
                         st.completed += 1
                         st.cells += r.cells
                         st.latencies.append(r.done - r.arrival)
+                        st.queue_waits.append(r.admitted - r.arrival)
+                        st.launch_waits.append(r.launched - r.admitted)
+                        st.device_times.append(r.done - r.launched)
                         st.last_done = max(st.last_done, t)
                     self.ex.release(h)
                 else:
