@@ -122,8 +122,10 @@ def cpu_freq_baseline(mats, budget_s):
 
 
 def large_section(L, h, dev, names, reps, golden):
-    """Each large matrix packed in HBM: ms_max_square, then ms_square_map_from_max, each timed
-    alone with HIP events after a 1 GiB write that evicts the caches."""
+    """Each large matrix packed in HBM: ms_max_square, ms_square_map_from_max and
+    ms_all_max_squares, each timed alone with HIP events after a 1 GiB write that evicts the
+    caches."""
+    import ctypes
     import numpy as np
     import torch
     import workloads as W
@@ -170,8 +172,39 @@ def large_section(L, h, dev, names, reps, golden):
         torch.cuda.synchronize()
         t_p = sum(e[0].elapsed_time(e[1]) for e in ev) / reps * 1e-3
         t_m = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
+        # all maximal squares (enumeration of every corner with dp = S), cold as above
+        ws_n = ctypes.c_size_t()
+        if L.ms_all_max_squares_workspace_size(h, m, n, ctypes.byref(ws_n)):
+            raise RuntimeError("ms_all_max_squares_workspace_size failed")
+        ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev)
+        cap = 1 << 20
+        pos = torch.empty(cap, dtype=torch.int64, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def all_max():
+            if L.ms_all_max_squares(h, d.data_ptr(), m, n, ldw, res.data_ptr(), pos.data_ptr(),
+                                    cap, cnt.data_ptr(), ws.data_ptr(), ws_n.value, sp):
+                raise RuntimeError("ms_all_max_squares failed")
+
+        all_max()
+        torch.cuda.synchronize()
+        count = int(cnt.item())
+        first = int(pos[0].item()) if count > 0 else -1
+        if count < 1 or first != g["row"] * n + g["col"]:
+            raise SystemExit("%s: first listed corner %d differs from the oracle's" % (name, first))
+        ea = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+        for r in range(reps):
+            flush.fill_((r + 3) & 0xff)
+            ea[r][0].record(stream)
+            all_max()
+            ea[r][1].record(stream)
+        torch.cuda.synchronize()
+        t_a = sum(e[0].elapsed_time(e[1]) for e in ea) / reps * 1e-3
+        del ws, pos
         cells = m * n
         rec = {"m": m, "n": n, "side": g["side"],
+               "all_max_squares": count, "all_max_us": t_a * 1e6,
+               "all_max_gcells_s": cells / t_a / 1e9,
                "max_square_us": t_p * 1e6, "max_square_gcells_s": cells / t_p / 1e9,
                "max_square_gbs": cells * PROBE_BYTES_PER_CELL / t_p / 1e9,
                "map_us": t_m * 1e6, "map_gcells_s": cells / t_m / 1e9,
@@ -180,8 +213,9 @@ def large_section(L, h, dev, names, reps, golden):
                "square_map_gcells_s": cells / (t_p + t_m) / 1e9}
         out[name] = rec
         log("large %s %dx%d S=%d: max_square %.1f us (%.0f Gcells/s), map %.1f us (%.0f GB/s, "
-            "%.0f%% of peak)" % (name, m, n, g["side"], t_p * 1e6, rec["max_square_gcells_s"],
-                                 t_m * 1e6, rec["map_gbs"], 100 * rec["map_frac"]))
+            "%.0f%% of peak), all %d maximal squares %.1f us"
+            % (name, m, n, g["side"], t_p * 1e6, rec["max_square_gcells_s"], t_m * 1e6,
+               rec["map_gbs"], 100 * rec["map_frac"], count, t_a * 1e6))
         del d, dp
         torch.cuda.empty_cache()
     del flush

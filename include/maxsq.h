@@ -147,6 +147,23 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
                                 int64_t count, ms_square *d_out, void *d_workspace,
                                 size_t workspace_bytes, void *stream);
 
+/*
+ * All maximal squares (the paper's conclusion: the method identifies every maximal square, not
+ * only its side).  d_max is the device result of ms_max_square on the same bits (side S).
+ * Writes the positions i * n + j of every cell whose side-map value equals S -- the bottom-right
+ * corners of all S x S all-ones squares -- in row-major order: the first min(count, capacity) of
+ * them to d_pos (int64), and the full count to *d_count (device int64).  S = 0 (or an empty
+ * matrix) gives count 0; a square wider than 3008 columns gives count -1 (not supported).
+ * d_workspace of ms_all_max_squares_workspace_size(m, n) bytes is caller-owned scratch.
+ * Invalid: as ms_max_square, plus capacity < 0, d_pos NULL with capacity > 0, d_count or (for
+ * m * n > 0) d_max NULL.
+ */
+ms_status ms_all_max_squares_workspace_size(ms_ctx *ctx, int64_t m, int64_t n, size_t *bytes);
+ms_status ms_all_max_squares(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                             int64_t ld_words, const ms_square *d_max, int64_t *d_pos,
+                             int64_t capacity, int64_t *d_count, void *d_workspace,
+                             size_t workspace_bytes, void *stream);
+
 /* Autotuning.  ms_num_candidates / ms_candidate enumerate the launch shapes this build can
  * run; ms_set_config forces one (NULL restores tuned/default choices); ms_get_config reports
  * the shape that would be used for an m x n matrix.  ms_autotune times every candidate on the

@@ -98,6 +98,9 @@ def lib():
             "ms_get_config": [_P, _I64, _I64, ctypes.POINTER(_Config)],
             "ms_autotune": [_P, _P, _I64, _I64, _I64, _P, _I64, _P],
             "ms_autotune_batched": [_P, _P, _P, _I64, _P, _P, ctypes.c_size_t, _P],
+            "ms_all_max_squares_workspace_size": [_P, _I64, _I64, ctypes.POINTER(ctypes.c_size_t)],
+            "ms_all_max_squares": [_P, _P, _I64, _I64, _I64, _P, _P, _I64, _P, _P,
+                                   ctypes.c_size_t, _P],
             "ms_autotune_save": [_P, ctypes.c_char_p],
             "ms_autotune_load": [_P, ctypes.c_char_p],
         }
@@ -321,6 +324,37 @@ def square_map_from_max(bits, n: int, result, ctx=None, stream=None, dp=None):
                                   dp.stride(0) if dp.numel() else max(n, 1), _stream(stream)),
            "ms_square_map_from_max")
     return dp
+
+
+def all_max_squares(bits, n: int, result=None, capacity: int | None = None, ctx=None,
+                    stream=None):
+    """Row-major positions i * n + j (int64 CUDA tensor) of the bottom-right corners of every
+    largest all-ones square of a packed matrix, and their count.  `result`: the int64 (3,)
+    device result of max_square(..., sync=False) for the same bits (computed if None).  With
+    the default capacity the call is repeated once with room for every corner if needed."""
+    torch = _torch()
+    _check_bits(bits, n)
+    m = bits.size(0)
+    if result is None:
+        result = max_square(bits, n, ctx=ctx, stream=stream, sync=False)
+    ws_n = ctypes.c_size_t()
+    _check(lib().ms_all_max_squares_workspace_size(_ctx(ctx), m, n, ctypes.byref(ws_n)),
+           "ms_all_max_squares_workspace_size")
+    ws = torch.empty(max(ws_n.value, 1), dtype=torch.uint8, device=bits.device)
+    count = torch.empty(1, dtype=torch.int64, device=bits.device)
+    cap = 4096 if capacity is None else int(capacity)
+    while True:
+        pos = torch.empty(max(cap, 1), dtype=torch.int64, device=bits.device)
+        _check(lib().ms_all_max_squares(_ctx(ctx), bits.data_ptr(), m, n, _ld_words(bits, n),
+                                        result.data_ptr(), pos.data_ptr(), cap,
+                                        count.data_ptr(), ws.data_ptr(), ws_n.value,
+                                        _stream(stream)), "ms_all_max_squares")
+        c = int(count.item())
+        if c < 0:
+            raise MaxsqError(5, "ms_all_max_squares (square wider than the enumeration supports)")
+        if capacity is not None or c <= cap:
+            return pos[: min(c, cap)], c
+        cap = c
 
 
 class Batch:

@@ -429,6 +429,35 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
     return hip_status(hipGraphLaunch(exec, st));
 }
 
+ms_status ms_all_max_squares_workspace_size(ms_ctx *ctx, int64_t m, int64_t n, size_t *bytes) {
+    (void)ctx;
+    if (!bytes || m < 0 || n < 0 || mul_overflows(m, std::max<int64_t>(n, 1)))
+        return MS_ERR_INVALID_ARGUMENT;
+    *bytes = mshost::all_max_layout(m, n).total;
+    return MS_OK;
+}
+
+ms_status ms_all_max_squares(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                             int64_t ld_words, const ms_square *d_max, int64_t *d_pos,
+                             int64_t capacity, int64_t *d_count, void *d_workspace,
+                             size_t workspace_bytes, void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (capacity < 0 || (capacity > 0 && !d_pos) || !d_count) return MS_ERR_INVALID_ARGUMENT;
+    const bool empty = m == 0 || n == 0;
+    if (!empty && (!d_max || !d_workspace)) return MS_ERR_INVALID_ARGUMENT;
+    if (!empty && workspace_bytes < mshost::all_max_layout(m, n).total)
+        return MS_ERR_WORKSPACE_TOO_SMALL;
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    mshost::LaunchEnv env{c->num_cus, (hipStream_t)stream};
+    return hip_status(mshost::launch_all_max(env, d_bits, m, n, ld_words, d_max, d_pos, capacity,
+                                             d_count, d_workspace));
+}
+
 int ms_num_candidates(void) { return mshost::NUM_PROBE_VARIANTS * 2 * 3; }
 
 ms_status ms_candidate(int index, ms_config *cfg) {

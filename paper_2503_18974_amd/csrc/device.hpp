@@ -801,4 +801,90 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
     }
 }
 
+// ----------------------------------------------------------------------------------------------
+// All maximal squares.  A cell is the bottom-right corner of a maximal square iff dp = S, and
+// since S is the largest side, iff dp >= S: per row, the horizontal erosion by S of the mask of
+// columns whose height is >= S (the frequency-array test of resolve_tile with k fixed at S).
+// The matrix is walked in units of ALL_ROWS rows x ALL_WORDS words; a unit's heights start from
+// a scan of at most S rows above it, over its columns and the S columns to their left.
+// ----------------------------------------------------------------------------------------------
+constexpr int ALL_ROWS = 128;
+constexpr int ALL_WORDS = 16;
+constexpr int64_t ALL_MAX_SIDE = 64 * (WAVE - ALL_WORDS - 1);  // window of one word per lane
+
+// Calls row_fn(i, mask, w0) for every row i of unit (uy, ux), where lane l's `mask` holds the
+// unit's cells of row i with dp >= k in word w0 + l.  k in [1, ALL_MAX_SIDE].
+template <class RowFn>
+__device__ void unit_rows_ge(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
+                             int64_t ldw, int64_t uy, int64_t ux, int32_t k, RowFn &&row_fn) {
+    const int lane = __lane_id();
+    const int64_t ra = uy * ALL_ROWS, rb = ra + ALL_ROWS < m ? ra + ALL_ROWS : m;
+    const int64_t xa = ux * ALL_WORDS * 64, xb = xa + ALL_WORDS * 64 < n ? xa + ALL_WORDS * 64 : n;
+    const int64_t nwords = (n + 63) >> 6;
+    const int64_t w0 = xa - k > 0 ? ((xa - k) >> 6) : 0;
+    const int64_t w1 = (xb + 63) >> 6;
+    const int64_t wl = w0 + lane;
+    const bool valid = wl < w1;
+    const int64_t wl_c = valid ? wl : w0;
+    const uint64_t wmask = !valid ? 0ull : (wl == nwords - 1 ? last_word_mask(n) : ~0ull);
+    uint64_t own = 0;
+    if (valid) {
+        const int64_t lo = (xa > wl * 64 ? xa : wl * 64) - wl * 64;
+        const int64_t hi = (xb < wl * 64 + 64 ? xb : wl * 64 + 64) - wl * 64;
+        if (hi > lo) own = (hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1)) << lo;
+    }
+    uint64_t P[HB];
+#pragma unroll
+    for (int p = 0; p < HB; ++p) P[p] = 0;
+    // heights at row ra - 1, clamped at k (only H >= k matters)
+    uint64_t acc = valid ? ~0ull : 0ull;
+    const int64_t rstop = ra - k > 0 ? ra - k : 0;
+    constexpr int FB = 16;
+    for (int64_t r0 = ra - 1; r0 >= rstop; r0 -= FB) {
+        uint64_t v[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const int64_t r = r0 - u >= rstop ? r0 - u : rstop;
+            v[u] = bits[r * ldw + wl_c];
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            if (r0 - u < rstop) break;
+            acc &= v[u] & wmask;
+            planes_inc_masked(P, acc);
+        }
+        if (!__ballot(acc != 0)) break;
+    }
+    for (int64_t i0 = ra; i0 < rb; i0 += FB) {
+        uint64_t v[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const int64_t r = i0 + u < rb ? i0 + u : rb - 1;
+            v[u] = bits[r * ldw + wl_c];
+        }
+        for (int u = 0; u < FB; ++u) {
+            const int64_t i = i0 + u;
+            if (i >= rb) break;
+            const uint64_t x = v[u] & wmask;
+            planes_inc_masked(P, ~0ull);
+#pragma unroll
+            for (int p = 0; p < HB; ++p) P[p] &= x;
+            row_fn(i, row_erode(planes_ge(P, k), k, lane) & own, w0);
+        }
+    }
+}
+
+// Exclusive prefix sum of a per-lane count over the wave (lane order), and the total.
+__device__ __forceinline__ uint32_t wave_excl_sum(uint32_t v, uint32_t *total) {
+    const int lane = __lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    *total = __shfl(x, WAVE - 1);
+    return x - v;
+}
+
 } // namespace msk

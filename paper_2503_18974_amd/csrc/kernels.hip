@@ -415,6 +415,99 @@ __global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------------- all squares
+// counts[i * nux + ux]: cells of row i, unit column ux whose side equals S (the maximum).
+__global__ __launch_bounds__(256) void k_allmax_count(const uint64_t *__restrict__ bits,
+                                                      int64_t m, int64_t n, int64_t ldw,
+                                                      const ms_square *__restrict__ maxsq,
+                                                      uint32_t *__restrict__ counts, int64_t nux,
+                                                      int64_t nunits) {
+    const int64_t S = uniform(maxsq->side);
+    if (S <= 0 || S > ALL_MAX_SIDE) return;  // nothing to list / reported by the scan
+    const int lane = __lane_id();
+    const int64_t wave = wave_index();
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    for (int64_t u = wave; u < nunits; u += nwave) {
+        const int64_t uy = u / nux, ux = u - uy * nux;
+        unit_rows_ge(bits, m, n, ldw, uy, ux, (int32_t)S,
+                     [&](int64_t i, uint64_t y, int64_t) {
+                         uint32_t tot;
+                         (void)wave_excl_sum((uint32_t)__popcll(y), &tot);
+                         if (lane == 0) counts[i * nux + ux] = tot;
+                     });
+    }
+}
+
+// One block: exclusive prefix of the counts in row-major (row, unit column) order, and the
+// total (0 when S = 0; -1 when S is wider than the enumeration supports).
+__global__ __launch_bounds__(1024) void k_allmax_scan(const ms_square *__restrict__ maxsq,
+                                                      const uint32_t *__restrict__ counts,
+                                                      int64_t entries,
+                                                      uint64_t *__restrict__ offsets,
+                                                      int64_t *__restrict__ total_out) {
+    __shared__ uint64_t part[1024];
+    const int64_t S = maxsq->side;
+    const int tid = threadIdx.x;
+    if (S <= 0 || S > ALL_MAX_SIDE) {
+        if (tid == 0) *total_out = S <= 0 ? 0 : -1;
+        return;
+    }
+    const int64_t per = (entries + 1023) / 1024;
+    const int64_t lo = tid * per < entries ? tid * per : entries;
+    const int64_t hi = lo + per < entries ? lo + per : entries;
+    uint64_t sum = 0;
+    for (int64_t e = lo; e < hi; ++e) sum += counts[e];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[tid] - sum;
+    for (int64_t e = lo; e < hi; ++e) {
+        offsets[e] = run;
+        run += counts[e];
+    }
+    if (tid == 1023) *total_out = (int64_t)part[1023];
+}
+
+// The positions i * n + j of those cells, in row-major order, the first `capacity` of them.
+__global__ __launch_bounds__(256) void k_allmax_write(const uint64_t *__restrict__ bits,
+                                                      int64_t m, int64_t n, int64_t ldw,
+                                                      const ms_square *__restrict__ maxsq,
+                                                      const uint64_t *__restrict__ offsets,
+                                                      int64_t nux, int64_t nunits,
+                                                      int64_t *__restrict__ pos, int64_t capacity) {
+    const int64_t S = uniform(maxsq->side);
+    if (S <= 0 || S > ALL_MAX_SIDE) return;
+    const int lane = __lane_id();
+    const int64_t wave = wave_index();
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    for (int64_t u = wave; u < nunits; u += nwave) {
+        const int64_t uy = u / nux, ux = u - uy * nux;
+        unit_rows_ge(bits, m, n, ldw, uy, ux, (int32_t)S,
+                     [&](int64_t i, uint64_t y, int64_t w0) {
+                         uint32_t tot;
+                         const uint32_t before = wave_excl_sum((uint32_t)__popcll(y), &tot);
+                         if (tot == 0) return;
+                         uint64_t k = offsets[i * nux + ux] + before;
+                         const int64_t rowpos = i * n + (w0 + lane) * 64;
+                         while (y) {
+                             const int b = __ffsll((long long)y) - 1;
+                             y &= y - 1;
+                             if ((int64_t)k < capacity) pos[k] = rowpos + b;
+                             ++k;
+                         }
+                     });
+    }
+}
+
+__global__ void k_write_i64(int64_t *dst, int64_t v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = v;
+}
+
 } // namespace msk
 
 // ====================================================================================== host
@@ -595,6 +688,41 @@ hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_
     case 1: return launch_batched_t<TS1>(env, d_mats, count, out, w, L);
     default: return launch_batched_t<TS2>(env, d_mats, count, out, w, L);
     }
+}
+
+AllMaxLayout all_max_layout(int64_t m, int64_t n) {
+    AllMaxLayout L{};
+    L.nux = cdiv(std::max<int64_t>(cdiv(n, 64), 1), (int64_t)msk::ALL_WORDS);
+    L.entries = std::max<int64_t>(m, 0) * L.nux;
+    L.counts = 0;
+    L.offsets = align256(sizeof(uint32_t) * (size_t)L.entries);
+    L.total = L.offsets + align256(sizeof(uint64_t) * (size_t)(L.entries + 1));
+    return L;
+}
+
+hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
+                          int64_t ldw, const ms_square *maxsq, int64_t *pos, int64_t capacity,
+                          int64_t *count, void *ws) {
+    if (m == 0 || n == 0) {
+        hipLaunchKernelGGL(msk::k_write_i64, dim3(1), dim3(64), 0, env.stream, count, (int64_t)0);
+        return hipGetLastError();
+    }
+    const AllMaxLayout L = all_max_layout(m, n);
+    auto *counts = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + L.counts);
+    auto *offsets = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + L.offsets);
+    const int64_t nunits = cdiv(m, (int64_t)msk::ALL_ROWS) * L.nux;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(nunits, 4),
+                                                                   (int64_t)env.num_cus * 8));
+    hipLaunchKernelGGL(msk::k_allmax_count, dim3((unsigned)blocks), dim3(256), 0, env.stream,
+                       bits, m, n, ldw, maxsq, counts, L.nux, nunits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(msk::k_allmax_scan, dim3(1), dim3(1024), 0, env.stream, maxsq, counts,
+                       L.entries, offsets, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(msk::k_allmax_write, dim3((unsigned)blocks), dim3(256), 0, env.stream,
+                       bits, m, n, ldw, maxsq, offsets, L.nux, nunits, pos, capacity);
+    return hipGetLastError();
 }
 
 } // namespace mshost

@@ -67,4 +67,14 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count);
 hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_mats,
                           int64_t count, ms_square *out, void *ws, const BatchLayout &L);
 
+// All maximal squares: workspace layout and launches.
+struct AllMaxLayout {
+    int64_t nux, entries;
+    size_t counts, offsets, total;
+};
+AllMaxLayout all_max_layout(int64_t m, int64_t n);
+hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
+                          int64_t ldw, const ms_square *maxsq, int64_t *pos, int64_t capacity,
+                          int64_t *count, void *ws);
+
 } // namespace mshost

@@ -120,3 +120,28 @@ def test_create_rejects_bad_args():
     h = ctypes.c_void_p()
     assert L.ms_create(ctypes.byref(h), -5) == INVALID
     assert L.ms_destroy(None) == INVALID
+
+
+@pytest.mark.parametrize("args", [
+    (None, P, 5, 5, 1, P, P, -1, P, P, 1 << 20, None),     # negative capacity
+    (None, P, 5, 5, 1, P, None, 4, P, P, 1 << 20, None),   # null positions with capacity
+    (None, P, 5, 5, 1, P, P, 4, None, P, 1 << 20, None),   # null count
+    (None, P, 5, 5, 1, None, P, 4, P, P, 1 << 20, None),   # null device result
+    (None, P, 5, 5, 1, P, P, 4, P, None, 1 << 20, None),   # null workspace
+    (None, None, 5, 5, 1, P, P, 4, P, P, 1 << 20, None),   # null bits
+    (None, P, 5, 130, 2, P, P, 4, P, P, 1 << 20, None),    # ld_words < ceil(n/64)
+])
+def test_all_max_squares_invalid(args):
+    assert M.lib().ms_all_max_squares(*args) == INVALID
+
+
+def test_all_max_squares_workspace():
+    L = M.lib()
+    size = ctypes.c_size_t()
+    assert L.ms_all_max_squares_workspace_size(None, -1, 5, ctypes.byref(size)) == INVALID
+    assert L.ms_all_max_squares_workspace_size(None, 1000, 2000, ctypes.byref(size)) == 0
+    big = size.value
+    assert L.ms_all_max_squares_workspace_size(None, 10, 2000, ctypes.byref(size)) == 0
+    assert 0 < size.value < big
+    # a workspace below the required size is refused before any device work
+    assert L.ms_all_max_squares(None, P, 1000, 2000, 32, P, P, 4, P, P, 16, None) == 2
