@@ -122,9 +122,9 @@ def cpu_freq_baseline(mats, budget_s):
 
 
 def large_section(L, h, dev, names, reps, golden):
-    """Each large matrix packed in HBM: ms_max_square, ms_square_map_from_max and
-    ms_all_max_squares, each timed alone with HIP events after a 1 GiB write that evicts the
-    caches."""
+    """Each large matrix packed in HBM: ms_max_square, ms_square_map (search + map in one call)
+    and ms_all_max_squares, each timed alone with HIP events after a 1 GiB write that evicts the
+    caches; the map's figures use ms_square_map's time minus ms_max_square's."""
     import ctypes
     import numpy as np
     import torch
@@ -158,6 +158,14 @@ def large_section(L, h, dev, names, reps, golden):
                              % (name, got, (g["side"], g["row"], g["col"])))
         if int(dp.max().item()) != g["side"]:
             raise SystemExit("%s: dp map maximum differs from the side" % name)
+        # ms_square_map runs the search and the map in one call (the map then sizes its halos
+        # from the search's per-tile bounds); the map's share is its time minus max_square's
+        res2 = torch.zeros(3, dtype=torch.int64, device=dev)
+        if L.ms_square_map(h, d.data_ptr(), m, n, ldw, dp.data_ptr(), n, res2.data_ptr(), sp):
+            raise RuntimeError("ms_square_map failed")
+        torch.cuda.synchronize()
+        if tuple(res2.cpu().tolist()) != got or int(dp.max().item()) != g["side"]:
+            raise SystemExit("%s: ms_square_map result differs" % name)
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
         for r in range(reps):
             flush.fill_(r & 0xff)
@@ -166,12 +174,12 @@ def large_section(L, h, dev, names, reps, golden):
             ev[r][1].record(stream)
             flush.fill_((r + 1) & 0xff)
             ev[r][2].record(stream)
-            L.ms_square_map_from_max(h, d.data_ptr(), m, n, ldw, res.data_ptr(), dp.data_ptr(), n,
-                                     sp)
+            L.ms_square_map(h, d.data_ptr(), m, n, ldw, dp.data_ptr(), n, res2.data_ptr(), sp)
             ev[r][3].record(stream)
         torch.cuda.synchronize()
         t_p = sum(e[0].elapsed_time(e[1]) for e in ev) / reps * 1e-3
-        t_m = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
+        t_sm = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
+        t_m = max(t_sm - t_p, 1e-9)
         # all maximal squares (enumeration of every corner with dp = S), cold as above
         ws_n = ctypes.c_size_t()
         if L.ms_all_max_squares_workspace_size(h, m, n, ctypes.byref(ws_n)):
@@ -210,7 +218,8 @@ def large_section(L, h, dev, names, reps, golden):
                "map_us": t_m * 1e6, "map_gcells_s": cells / t_m / 1e9,
                "map_gbs": cells * MAP_BYTES_PER_CELL / t_m / 1e9,
                "map_frac": cells * MAP_BYTES_PER_CELL / t_m / 1e9 / HBM_PEAK_GBS,
-               "square_map_gcells_s": cells / (t_p + t_m) / 1e9}
+               "square_map_us": t_sm * 1e6,
+               "square_map_gcells_s": cells / t_sm / 1e9}
         out[name] = rec
         log("large %s %dx%d S=%d: max_square %.1f us (%.0f Gcells/s), map %.1f us (%.0f GB/s, "
             "%.0f%% of peak), all %d maximal squares %.1f us"
@@ -220,6 +229,40 @@ def large_section(L, h, dev, names, reps, golden):
         torch.cuda.empty_cache()
     del flush
     torch.cuda.empty_cache()
+    return out
+
+
+def hbm_achievable(dev, reps=5):
+    """Bandwidth a plain streaming kernel reaches on this device, read-only (a max-reduction
+    over 1 GiB), write-only (a 1 GiB fill) and copy (512 MiB each way), best of `reps`: the
+    measured ceiling the roofline fractions can also be read against."""
+    import torch
+    x = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device=dev)
+    y = torch.empty(FLUSH_BYTES // 8, dtype=torch.int32, device=dev)
+    z = torch.empty_like(y)
+    x.fill_(1)
+    y.fill_(2)
+    torch.cuda.synchronize()
+
+    def best(fn, nbytes):
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e-3)
+        return nbytes / min(t) / 1e9
+
+    out = {"read_gbs": best(lambda: torch.amax(x), FLUSH_BYTES),
+           "write_gbs": best(lambda: x.fill_(3), FLUSH_BYTES),
+           "copy_gbs": best(lambda: z.copy_(y), FLUSH_BYTES),
+           "what": "best of %d: max-reduction over 1 GiB int32 (read), 1 GiB fill (write), "
+                   "512 MiB device copy (read + write bytes)" % reps}
+    del x, y, z
+    log("achievable HBM: read %.0f GB/s, write %.0f GB/s, copy %.0f GB/s"
+        % (out["read_gbs"], out["write_gbs"], out["copy_gbs"]))
     return out
 
 
@@ -377,6 +420,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--streams", type=int, default=4,
+                    help="streams for the multi-stream grid step (1 skips it)")
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--c4-reps", type=int, default=10)
     args = ap.parse_args()
@@ -495,6 +540,47 @@ def main():
         graph_value = cells * args.steps / (time.perf_counter() - t0) / 1e9
         log("graph-replayed step: %.1f Gcells/s" % graph_value)
 
+    # the same per-matrix calls spread over several streams, one context per stream (a context's
+    # scratch serves one stream at a time), matrices dealt largest first to the least-loaded
+    # stream; the small matrices' launches are latency-bound, so independent ones overlap
+    multi = None
+    if args.streams > 1:
+        nst = args.streams
+        streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
+        ctxs = [M.Context() for _ in range(nst)]
+        load = [0] * nst
+        lanes = [[] for _ in range(nst)]
+        for i in sorted(range(len(calls)), key=lambda k: -calls[k][0]):
+            s = min(range(nst), key=lambda k: load[k])
+            load[s] += calls[i][0] ** 2
+            lanes[s].append(calls[i])
+
+        def mstep():
+            for s in range(nst):
+                hs, ss = ctxs[s].handle, streams[s].cuda_stream
+                for (n, pa, pb, ldw, pdp, pres) in lanes[s]:
+                    if (L.ms_pack_u8(hs, pa, n, n, n, pb, ldw, ss)
+                            or L.ms_max_square(hs, pb, n, n, ldw, pres, ss)
+                            or L.ms_square_map_from_max(hs, pb, n, n, ldw, pres, pdp, n, ss)):
+                        raise RuntimeError("per-matrix call failed on stream %d" % s)
+
+        RES.fill_(-9)
+        torch.cuda.synchronize()
+        for _ in range(max(args.warmup, 1)):
+            mstep()
+        torch.cuda.synchronize()
+        if not np.array_equal(RES.cpu().numpy(), res):
+            raise SystemExit("multi-stream step gives different results")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mstep()
+        torch.cuda.synchronize()
+        t_ms = (time.perf_counter() - t0) / args.steps
+        multi = {"streams": nst, "gcells_s": cells / t_ms / 1e9, "ms_per_step": t_ms * 1e3}
+        for c in ctxs:
+            c.close()
+        log("%d streams: %.3f ms per step, %.1f Gcells/s" % (nst, t_ms * 1e3, multi["gcells_s"]))
+
     # spot-check one map against the oracle-derived invariant max(dp) == S
     for i in (0, len(mats) - 1):
         if int(DP[i].max().item()) != int(res[i][0]):
@@ -533,6 +619,7 @@ def main():
         }
         log("batched %.3f ms vs per-matrix loop %.3f ms" % (t_b, t_p))
 
+    extra["hbm_achievable"] = hbm_achievable(dev)
     if not args.no_large:
         extra["large"] = large_section(L, h, dev, [x for x in args.large.split(",") if x],
                                        args.large_reps, golden_all)
@@ -576,10 +663,13 @@ def main():
             "bytes_per_cell": MAP_BYTES_PER_CELL,
             "algorithmic_bytes_per_launch": map_bytes_avg,
             "source_fingerprint": kernel_fingerprint(),
+            "frac_of_achievable_write": achieved / extra["hbm_achievable"]["write_gbs"],
         },
     }
     if graph_value is not None:
         extra["graph_step_gcells_s"] = graph_value
+    if multi is not None:
+        extra["multi_stream_step"] = multi
     out.update(extra)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)

@@ -163,8 +163,9 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     }
     const int64_t words = std::max<int64_t>(nwords, c->state_words);
     const int64_t sat = std::max<int64_t>(tiles, c->sat_bytes);
+    // header | serial state | saturation bytes | per-tile bounds (int32)
     const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t) +
-                         (size_t)sat;
+                         (((size_t)sat + 255) & ~(size_t)255) + (size_t)sat * sizeof(int32_t);
     if (c->scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
@@ -188,6 +189,9 @@ mshost::ScratchHeader *hdr_of(ms_ctx *c) { return static_cast<mshost::ScratchHea
 uint8_t *sat_of(ms_ctx *c) {
     return static_cast<uint8_t *>(c->scratch) + sizeof(mshost::ScratchHeader) +
            (size_t)c->state_words * 64 * 2 * sizeof(int32_t);
+}
+int32_t *bounds_of(ms_ctx *c) {
+    return reinterpret_cast<int32_t *>(sat_of(c) + (((size_t)c->sat_bytes + 255) & ~(size_t)255));
 }
 int32_t *state_of(ms_ctx *c) {
     return reinterpret_cast<int32_t *>(static_cast<char *>(c->scratch) +
@@ -216,7 +220,7 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
         e = mshost::launch_write_result(env, out, hdr_of(c), out ? 1 : 0);
     } else {
         e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
-                                      state_of(c), sat_of(c), out);
+                                      state_of(c), sat_of(c), bounds_of(c), out);
     }
     if (e != hipSuccess) {
         c->dirty = true;
@@ -323,9 +327,12 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
     s = run_max_square(c, cfg, d_bits, m, n, ld_words, d_out, st);
     if (s != MS_OK || m == 0 || n == 0) return s;
     mshost::LaunchEnv env{c->num_cus, st};
+    // the search just ran on these bits: its per-tile bounds let the map size halos by region
+    const mshost::MapRegions regions{bounds_of(c), mshost::probe_tile_rows(cfg.probe_variant),
+                                     cdiv(cdiv(n, 64), mshost::PROBE_TILE_WORDS)};
     hipError_t e = mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m, n,
                                              ld_words, d_dp, ld_dp, &hdr_of(c)->result,
-                                             state_of(c));
+                                             state_of(c), &regions);
     return hip_status(e);
 }
 

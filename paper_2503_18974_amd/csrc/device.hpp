@@ -137,11 +137,21 @@ struct WaveLds {
     int cap = LDS_WORDS;
 };
 
-template <int NGMAX, int CPL, bool STORE, bool TRACK>
+// Which owned cells a pass stores, when the map is split by tile class: bit k of cls[g] is set
+// when the lane's columns of group g in tile row ty0 + k (tile rows of `tile_rows` rows) belong
+// to the pass.  With `on` false every owned cell is stored.
+template <int NGMAX>
+struct StoreClass {
+    bool on = false;
+    int64_t tile_rows = 1, ty0 = 0;
+    uint64_t cls[NGMAX];
+};
+
+template <int NGMAX, int CPL, bool STORE, bool TRACK, bool CLASSED = false>
 __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n, int64_t rh,
                       int64_t ra, int64_t rb, int64_t xh, int64_t xa, int64_t xb, int ng,
                       int32_t *__restrict__ dp, int64_t ld_dp, bool vec_ok, Track &tr,
-                      WaveLds lds) {
+                      WaveLds lds, const StoreClass<NGMAX> &sc = StoreClass<NGMAX>{}) {
     static_assert(CPL == 4 || CPL == 8, "columns per lane");
     static_assert(NGMAX * CPL <= 64, "window words must fit one wave");
     rh = uniform(rh);
@@ -236,6 +246,7 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                 }
             }
             int32_t dleft_old = 0;  // previous-row dp just left of the group
+            const int krow = (CLASSED && own_row) ? (int)(i / sc.tile_rows - sc.ty0) : 0;
 #pragma unroll
             for (int g = 0; g < NGMAX; ++g) {
                 if (g < ng) {
@@ -263,7 +274,7 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                         dprev = old;
                     }
                     const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
-                    if (own_row) {
+                    if (own_row && (!CLASSED || ((sc.cls[g] >> krow) & 1))) {
                         if (STORE) {
                             int32_t *p = dp + i * ld_dp + col;
                             if (col >= xa && col + CPL <= xb) {
@@ -443,33 +454,52 @@ struct TileSink {
     unsigned long long *key;   // atomicMax target: (side, first position) of the best square
 };
 
-// Saturation bytes of the tiles a wave visits (tile t0 + k * stride for k < 64), written with
-// one store per 64 tiles: a store per tile would make the next tile's loads wait for it.
+// Per-tile outcome of the probe for the tiles a wave visits (tile t0 + k * stride, k < 64):
+// the saturation byte (read by the resolve pass) and, when `bounds` is set, an upper bound on
+// the tile's largest side (read by the dp map; -1 for a saturated tile, which the resolve pass
+// replaces).  Written with one store per array per 64 tiles: a store per tile would make the
+// next tile's loads wait for it.
+constexpr int32_t SAT_BOUND = -1;
+// Largest side the narrow dp-map kernel (512-column windows) covers.
+constexpr int32_t MAP_NARROW_REACH = 448;
+// When a square exceeds that reach, the map is split by tile: tiles bounded by REGION_SMALL are
+// mapped by the narrow kernel with a REGION_SMALL halo, the others by the wide kernel.
+constexpr int32_t REGION_SMALL = 64;
+
 struct SatBatch {
     uint8_t *base;
+    int32_t *bounds = nullptr;
     int64_t t0 = 0, stride = 1;
     uint64_t bits = 0;
     int count = 0, nsat = 0;
-    __device__ void add(int64_t t, bool s) {
-        const int32_t su = uniform((int32_t)s);   // wave-uniform: keep the state in SGPRs
+    int32_t mine = 0;  // lane k: the bound of the k-th collected tile
+    __device__ void add(int64_t t, int32_t bound) {
+        const int32_t bu = uniform(bound);   // wave-uniform: keep the state in SGPRs
+        const int32_t su = bu < 0 ? 1 : 0;
         if (count == 0) t0 = uniform(t);
         bits |= (uint64_t)su << count;
         nsat += su;
+        if (__lane_id() == count) mine = bu;
         if (++count == 64) flush();
     }
     __device__ void flush() {
         const int lane = __lane_id();
-        if (lane < count) base[t0 + lane * stride] = (uint8_t)((bits >> lane) & 1);
+        if (lane < count) {
+            base[t0 + lane * stride] = (uint8_t)((bits >> lane) & 1);
+            if (bounds) bounds[t0 + lane * stride] = mine;
+        }
         bits = 0;
         count = 0;
     }
 };
 
 // Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
-// key with the first owned cell of E_k.  Returns whether E_KC is non-empty among the owned cells
-// ("saturated": the resolve pass, resolve_tile, finishes such a tile).
+// key with the first owned cell of E_k.  Returns an upper bound on the tile's largest side (exact
+// unless the search stopped early because the tile could not reach the best side so far), or
+// SAT_BOUND when E_KC is non-empty among the owned cells ("saturated": the resolve pass,
+// resolve_tile, finishes such a tile).
 template <class TS>
-__device__ __forceinline__ bool tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+__device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int64_t ty, int64_t tx, const TileSink &sink) {
     constexpr int RPL = TS::RPL;
     m = uniform(m);
@@ -502,7 +532,7 @@ __device__ __forceinline__ bool tile_search(const uint64_t *__restrict__ bits, i
     const bool lane_ok = wl != 0 && wvalid;
     // best side found so far by any tile (read now so the load overlaps the erosion steps)
     const int64_t best = key_side(load_relaxed(sink.key));
-    if (!any_owned<TS>(E, rg, lane_ok)) return false;
+    if (!any_owned<TS>(E, rg, lane_ok)) return 0;
 
     int cur = 1;
     bool saturated = true;
@@ -519,7 +549,7 @@ __device__ __forceinline__ bool tile_search(const uint64_t *__restrict__ bits, i
     }
     if (!saturated) {
         // the tile's side is in [cur, 2 cur - 1]; skip it if it cannot reach the best so far
-        if (2 * cur - 1 < best) return false;
+        if (2 * cur - 1 < best) return 2 * cur - 1;
         for (int d = cur >> 1; d >= 1; d >>= 1) {
             erode_by<RPL>(E, T, d, rg, wl);
             if (any_owned<TS>(T, rg, lane_ok)) {
@@ -527,9 +557,9 @@ __device__ __forceinline__ bool tile_search(const uint64_t *__restrict__ bits, i
                 for (int r = 0; r < RPL; ++r) E[r] = T[r];
                 cur += d;
             }
-            if (cur + d - 1 < best) return false;
+            if (cur + d - 1 < best) return cur + d - 1;
         }
-        if (cur < best) return false;
+        if (cur < best) return cur;
     }
     // first owned cell of E_cur in row-major order
     int64_t pos = INT64_MAX;
@@ -543,7 +573,7 @@ __device__ __forceinline__ bool tile_search(const uint64_t *__restrict__ bits, i
     }
     pos = wave_min_i64(pos);
     if (lane == 0) atomicMax(sink.key, make_key(cur, pos));
-    return saturated;
+    return saturated ? SAT_BOUND : cur;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -759,11 +789,16 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
     return true;
 }
 
+// Records the tile's bound when the caller keeps bounds.
+__device__ __forceinline__ void note_bound(int32_t *bounds, int64_t t, int64_t bound) {
+    if (bounds && __lane_id() == 0) bounds[t] = (int32_t)bound;
+}
+
 template <class TS>
 __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
                              int64_t ldw, int64_t ty, int64_t tx, int64_t ntx,
                              const uint8_t *__restrict__ sat, unsigned long long *key,
-                             uint32_t *serial_flag) {
+                             uint32_t *serial_flag, int32_t *bounds = nullptr) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
     m = uniform(m);
@@ -777,7 +812,10 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
     const int64_t mn = m < n ? m : n;
     ucap = ucap < mn ? ucap : mn;
     const int64_t g = uniform(key_side(load_relaxed(key)));
-    if (ucap < g) return;  // cannot reach the best side found so far
+    if (ucap < g) {  // cannot reach the best side found so far
+        note_bound(bounds, ty * ntx + tx, ucap);
+        return;
+    }
     // one pass at the bound when its window fits (exact at once), else doubling from twice
     // the best side so far (the bound is loose where most tiles saturate)
     const int64_t w0cap = tx * OWN_COLS - ucap > 0 ? ((tx * OWN_COLS - ucap) >> 6) : 0;
@@ -795,9 +833,153 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
         best = uniform(best);
         if (best < U || U >= ucap) {
             if (lane == 0 && best > 0) atomicMax(key, make_key(best, bpos));
+            note_bound(bounds, ty * ntx + tx, best);
             return;
         }
         U = 2 * (int64_t)best;
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// dprun_block: the rows-parallel recurrence over a window of up to 8 groups of 256 columns shared
+// by the 4 waves of a block (wave w owns groups 2w and 2w + 1), for squares too wide for a
+// one-wave window.  The window's packed words and entering row runs are staged once per row
+// chunk for the whole block; dp[i-1][j-1] crosses from wave w-1 to wave w through a
+// double-buffered LDS slot written after each row, with one barrier per row.  Every loop trip
+// count here is uniform over the block, so all waves meet every barrier.
+// ----------------------------------------------------------------------------------------------
+constexpr int BLK_WORDS = 4096;  // staged packed words per block
+
+struct BlockLds {
+    uint64_t *x;     // BLK_WORDS packed words
+    int32_t *c;      // BLK_WORDS entering row runs
+    int32_t *slot;   // [2][4] last-column dp of each wave, by row parity
+};
+
+template <bool CLASSED>
+__device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
+                            int64_t rh, int64_t ra, int64_t rb, int64_t xh, int64_t xa,
+                            int64_t xb, int ng, int32_t *__restrict__ dp, int64_t ld_dp,
+                            bool vec_ok, BlockLds L, const StoreClass<2> &sc) {
+    constexpr int CPL = 4, GW = 64 * CPL, LPW = 64 / CPL, GPW = 2, NTH = 256;
+    rh = uniform(rh);
+    ra = uniform(ra);
+    rb = uniform(rb);
+    xh = uniform(xh);
+    xa = uniform(xa);
+    xb = uniform(xb);
+    ng = uniform(ng);
+    ldw = uniform(ldw);
+    n = uniform(n);
+    ld_dp = uniform(ld_dp);
+    const int tid = threadIdx.x;
+    const int wv = tid / WAVE, lane = tid % WAVE;
+    const int q = lane / LPW;
+    const int b = (lane % LPW) * CPL;
+    const int64_t nwords = (n + 63) >> 6;
+    const uint64_t lastmask = last_word_mask(n);
+    const int nww = ng * CPL;
+    const int rc_max = BLK_WORDS / nww;
+    const int fl_w = tid % nww, fl_r = tid / nww, fl_rpp = NTH / nww;
+    const int64_t fl_word = (xh >> 6) + fl_w;
+    const bool fl_ok = fl_r < fl_rpp && fl_word < nwords;
+    const uint64_t fl_mask = (fl_word == nwords - 1) ? lastmask : ~0ull;
+    const int64_t fl_wc = fl_word < nwords ? fl_word : nwords - 1;
+
+    int32_t H[GPW][CPL], D[GPW][CPL];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            H[g][t] = 0;
+            D[g][t] = 0;
+        }
+    if (tid < 8) L.slot[tid] = 0;   // zero state left of every wave before the first row
+
+    for (int64_t r0 = rh; r0 < rb; r0 += rc_max) {
+        const int rc = (int)(rb - r0 < rc_max ? rb - r0 : rc_max);
+        constexpr int FB = 8;
+        for (int rb0 = fl_r; rb0 < rc; rb0 += FB * fl_rpp) {
+            uint64_t v[FB];
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int r = rb0 + u * fl_rpp;
+                const int r_c = r < rc ? r : rc - 1;
+                v[u] = bits[(r0 + r_c) * ldw + fl_wc];
+            }
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int r = rb0 + u * fl_rpp;
+                if (r < rc && fl_r < fl_rpp) L.x[r * nww + fl_w] = fl_ok ? (v[u] & fl_mask) : 0ull;
+            }
+        }
+        __syncthreads();
+        for (int r = tid; r < rc; r += NTH) {
+            int32_t run = 0;
+            for (int w = 0; w < nww; ++w) {
+                const uint64_t v = L.x[r * nww + w];
+                L.c[r * nww + w] = run;
+                run = (v == ~0ull) ? run + 64 : leading_ones(v);
+            }
+        }
+        __syncthreads();
+        for (int rr = 0; rr < rc; ++rr) {
+            const int64_t i = r0 + rr;
+            const bool own_row = i >= ra;
+            const int par = (int)(i & 1);
+            // previous-row dp just left of this wave's first group (from wave wv - 1)
+            int32_t dleft_old = wv > 0 ? L.slot[par * 4 + wv - 1] : 0;
+            const int krow = (CLASSED && own_row) ? (int)(i / sc.tile_rows - sc.ty0) : 0;
+#pragma unroll
+            for (int gl = 0; gl < GPW; ++gl) {
+                const int g = wv * GPW + gl;
+                if (g < ng) {
+                    const uint64_t x = L.x[rr * nww + g * CPL + q];
+                    const int32_t carry = L.c[rr * nww + g * CPL + q];
+                    int32_t wrun = carry;
+                    if (b != 0) {
+                        const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
+                        wrun = (lo == b) ? b + carry : lo;
+                    }
+                    const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
+                    int32_t dprev = from_left_lane(D[gl][CPL - 1], dleft_old);
+                    dleft_old = __builtin_amdgcn_readlane(D[gl][CPL - 1], WAVE - 1);
+                    int32_t w = wrun;
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) {
+                        const int32_t mk = -(int32_t)((nib >> t) & 1u);
+                        const int32_t h = (H[gl][t] + 1) & mk;
+                        w = (w + 1) & mk;
+                        const int32_t old = D[gl][t];
+                        int32_t d = h < w ? h : w;
+                        d = d < dprev + 1 ? d : dprev + 1;
+                        H[gl][t] = h;
+                        D[gl][t] = d;
+                        dprev = old;
+                    }
+                    const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
+                    if (own_row && (!CLASSED || ((sc.cls[gl] >> krow) & 1))) {
+                        int32_t *p = dp + i * ld_dp + col;
+                        if (col >= xa && col + CPL <= xb) {
+                            if (vec_ok) {
+                                *reinterpret_cast<int4 *>(p) =
+                                    make_int4(D[gl][0], D[gl][1], D[gl][2], D[gl][3]);
+                            } else {
+#pragma unroll
+                                for (int t = 0; t < CPL; ++t) p[t] = D[gl][t];
+                            }
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < CPL; ++t)
+                                if (col + t >= xa && col + t < xb) p[t] = D[gl][t];
+                        }
+                    }
+                }
+            }
+            // this row's last-column dp of the wave, for wave wv + 1 at the next row
+            if (lane == WAVE - 1) L.slot[(par ^ 1) * 4 + wv] = D[GPW - 1][CPL - 1];
+            __syncthreads();
+        }
     }
 }
 

@@ -96,10 +96,12 @@ template <class TS>
 __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits, int64_t m,
                                                int64_t n, int64_t ldw, int64_t ntiles,
                                                int64_t ntx, mshost::ScratchHeader *hdr,
-                                               uint8_t *__restrict__ sat) {
+                                               uint8_t *__restrict__ sat,
+                                               int32_t *__restrict__ bounds) {
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     SatBatch sb{sat};
+    sb.bounds = bounds;
     sb.stride = nwave;
     for (int64_t t = wave; t < ntiles; t += nwave) {
         const int64_t ty = t / ntx, tx = t - ty * ntx;
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
                                                  int64_t n, int64_t ldw, int64_t ntiles,
                                                  int64_t ntx, mshost::ScratchHeader *hdr,
                                                  const uint8_t *__restrict__ sat,
+                                                 int32_t *__restrict__ bounds,
                                                  int32_t *serial_state, ms_square *out) {
     const int lane = __lane_id();
     const int64_t wave = wave_index();
@@ -176,7 +179,8 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
             b &= b - 1;
             const int64_t tt = base + (int64_t)l * nwave;
             const int64_t ty = tt / ntx, tx = tt - ty * ntx;
-            resolve_tile<TS>(bits, m, n, ldw, ty, tx, ntx, sat, &hdr->key, &hdr->serial_flag);
+            resolve_tile<TS>(bits, m, n, ldw, ty, tx, ntx, sat, &hdr->key, &hdr->serial_flag,
+                             bounds);
         }
     }
     __threadfence();
@@ -195,23 +199,35 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
 // serves the common small squares and a wide one the rest; the other exits at once.
 // Band height: at least band_rows and 4 S (so the S-row head start costs at most a quarter),
 // halved while that leaves fewer items than waves, down to 2 S (or 16 rows).
+// Region mode (bounds != nullptr, only for a search that ran in the same call): each probe tile
+// carries an upper bound on its largest side.  When S exceeds the narrow reach, the narrow kernel
+// uses REGION_SMALL halos and stores only cells of tiles bounded by REGION_SMALL; the wide kernel
+// uses S, skips items touching no other tile, and stores only cells of the other tiles.  A cell
+// is exact whenever the halo is at least its own dp.
 template <int NGMAX, int CPL>
 __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits, int64_t m,
                                                int64_t n, int64_t ldw, int32_t *__restrict__ dp,
                                                int64_t ld_dp,
                                                const ms_square *__restrict__ maxsq,
                                                int64_t band_rows, int32_t *serial_state,
-                                               int vec_ok, int64_t s_lo, int serial_beyond) {
+                                               int vec_ok, int64_t s_lo, int serial_beyond,
+                                               const int32_t *__restrict__ bounds,
+                                               int64_t tile_rows, int64_t tile_ntx) {
     constexpr int64_t GW = 64 * CPL;
     constexpr int64_t WIN = NGMAX * GW;
     constexpr int64_t REACH = WIN - 64;   // largest S whose halo leaves a 64-column output
     constexpr int LDSW = NGMAX * CPL <= 8 ? LDS_WORDS / 2 : LDS_WORDS;
+    constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
     __shared__ uint64_t lx[4][LDSW];
     __shared__ int32_t lc[4][LDSW];
     const WaveLds lds{lx[threadIdx.x / WAVE], lc[threadIdx.x / WAVE], LDSW};
     const int64_t S = uniform(maxsq->side);
     if (S <= s_lo) return;
-    const int64_t hc = (S + 63) & ~(int64_t)63;
+    const bool region = bounds != nullptr && S > MAP_NARROW_REACH;
+    const bool wide_pass = s_lo >= 0;           // this launch owns the tiles beyond the reach
+    int64_t Sg = S;                             // the side the halos must cover
+    if (region && !wide_pass) Sg = REGION_SMALL;
+    const int64_t hc = (Sg + 63) & ~(int64_t)63;
     if (hc > REACH) {
         // too large for this window: one wave sweeps the whole matrix (widest kernel only)
         if (serial_beyond && blockIdx.x == 0 && threadIdx.x < WAVE) {
@@ -227,21 +243,135 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
     const int64_t nwin = (n + ow - 1) / ow;
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-    int64_t R = band_rows > 4 * S ? band_rows : 4 * S;
-    const int64_t rmin = 2 * S > 16 ? 2 * S : 16;
+    int64_t R = band_rows > 4 * Sg ? band_rows : 4 * Sg;
+    const int64_t rmin = 2 * Sg > 16 ? 2 * Sg : 16;
     while (R > rmin && ((m + R - 1) / R) * nwin < nwave) R = (R / 2 > rmin) ? R / 2 : rmin;
+    if (region) {
+        // the wide pass touches few items: short bands spread them over more waves; either pass
+        // keeps an item within 32 tile rows (one mask bit per tile row)
+        if (wide_pass) R = 2 * tile_rows;
+        R = R < 32 * tile_rows ? R : 32 * tile_rows;
+    }
     R = R < m ? R : m;
     const int64_t items = ((m + R - 1) / R) * nwin;
+    const int lane = __lane_id();
     Track dummy{0, 0};
     for (int64_t it = wave; it < items; it += nwave) {
         const int64_t b = it / nwin, wdx = it - b * nwin;
         const int64_t ra = b * R, rb = ra + R < m ? ra + R : m;
+        const int64_t rh = ra - Sg > 0 ? ra - Sg : 0;
+        const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
+        const int64_t xh = xa - hc > 0 ? xa - hc : 0;
+        const int ngi = (int)((xb - xh + GW - 1) / GW);
+        StoreClass<NGMAX> sc;
+        if (region) {
+            sc.on = true;
+            sc.tile_rows = tile_rows;
+            sc.ty0 = ra / tile_rows;
+            const int64_t nk = (rb - 1) / tile_rows - sc.ty0 + 1;  // <= 33
+            bool any = false;
+#pragma unroll
+            for (int g = 0; g < NGMAX; ++g) {
+                sc.cls[g] = 0;
+                const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
+                if (g < ngi && col >= xa && col < xb) {
+                    const int64_t tc = col / TILE_COLS;
+                    for (int64_t k = 0; k < nk; ++k) {
+                        const int32_t bnd = bounds[(sc.ty0 + k) * tile_ntx + tc];
+                        const bool big = bnd < 0 || bnd > REGION_SMALL;
+                        if (big == wide_pass) sc.cls[g] |= 1ull << k;
+                    }
+                }
+                any |= sc.cls[g] != 0;
+            }
+            if (!__ballot(any)) continue;  // nothing of this pass's class here
+            dprun<NGMAX, CPL, true, false, true>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp,
+                                                 ld_dp, vec_ok != 0, dummy, lds, sc);
+        } else {
+            dprun<NGMAX, CPL, true, false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp,
+                                           vec_ok != 0, dummy, lds);
+        }
+    }
+}
+
+// Wide dp map (448 < S <= 1984): windows of 2048 columns, one window per block (dprun_block),
+// items distributed per block so that the block's barriers stay uniform.  Region mode as in
+// k_dpmap: items touching no tile bounded above REGION_SMALL are skipped, and only cells of such
+// tiles are stored.  Beyond 1984 one wave sweeps the whole matrix.
+__global__ __launch_bounds__(256) void k_dpmap_wide(const uint64_t *__restrict__ bits, int64_t m,
+                                                    int64_t n, int64_t ldw,
+                                                    int32_t *__restrict__ dp, int64_t ld_dp,
+                                                    const ms_square *__restrict__ maxsq,
+                                                    int64_t band_rows, int32_t *serial_state,
+                                                    int vec_ok,
+                                                    const int32_t *__restrict__ bounds,
+                                                    int64_t tile_rows, int64_t tile_ntx) {
+    constexpr int64_t GW = 256, NGB = 8, WIN = NGB * GW, REACH = WIN - 64;
+    constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
+    __shared__ uint64_t lx[BLK_WORDS];
+    __shared__ int32_t lc[BLK_WORDS];
+    __shared__ int32_t lslot[8];
+    const BlockLds L{lx, lc, lslot};
+    const int64_t S = uniform(maxsq->side);
+    if (S <= MAP_NARROW_REACH) return;
+    const int64_t hc = (S + 63) & ~(int64_t)63;
+    if (hc > REACH) {
+        if (blockIdx.x == 0 && threadIdx.x < WAVE) {
+            const int64_t nw64 = ((n + 63) >> 6) * 64;
+            Track tr{0, INT64_MAX};
+            serial_dp<true>(bits, m, n, ldw, dp, ld_dp, serial_state, serial_state + nw64, tr);
+        }
+        return;
+    }
+    const bool region = bounds != nullptr;
+    const int64_t ow = WIN - hc;
+    const int64_t nwin = (n + ow - 1) / ow;
+    const int64_t nblk = gridDim.x;
+    int64_t R;
+    if (region) {
+        R = 2 * tile_rows;  // few items touch wide tiles: short bands spread them out
+    } else {
+        R = band_rows > 4 * S ? band_rows : 4 * S;
+        const int64_t rmin = 2 * S;
+        while (R > rmin && ((m + R - 1) / R) * nwin < nblk) R = (R / 2 > rmin) ? R / 2 : rmin;
+    }
+    R = R < m ? R : m;
+    const int64_t items = ((m + R - 1) / R) * nwin;
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    for (int64_t it = blockIdx.x; it < items; it += nblk) {
+        const int64_t bnd_i = it / nwin, wdx = it - bnd_i * nwin;
+        const int64_t ra = bnd_i * R, rb = ra + R < m ? ra + R : m;
         const int64_t rh = ra - S > 0 ? ra - S : 0;
         const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
         const int64_t xh = xa - hc > 0 ? xa - hc : 0;
         const int ngi = (int)((xb - xh + GW - 1) / GW);
-        dprun<NGMAX, CPL, true, false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp,
-                                       vec_ok != 0, dummy, lds);
+        if (region) {
+            StoreClass<2> sc;
+            sc.on = true;
+            sc.tile_rows = tile_rows;
+            sc.ty0 = ra / tile_rows;
+            const int64_t nk = (rb - 1) / tile_rows - sc.ty0 + 1;  // 2 or 3
+            bool any = false;
+#pragma unroll
+            for (int gl = 0; gl < 2; ++gl) {
+                sc.cls[gl] = 0;
+                const int64_t col = xh + (int64_t)(wv * 2 + gl) * GW + (int64_t)lane * 4;
+                if (wv * 2 + gl < ngi && col >= xa && col < xb) {
+                    const int64_t tc = col / TILE_COLS;
+                    for (int64_t k = 0; k < nk; ++k) {
+                        const int32_t bv = bounds[(sc.ty0 + k) * tile_ntx + tc];
+                        if (bv < 0 || bv > REGION_SMALL) sc.cls[gl] |= 1ull << k;
+                    }
+                }
+                any |= sc.cls[gl] != 0;
+            }
+            if (!__syncthreads_or(any)) continue;   // block-uniform
+            dprun_block<true>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp, vec_ok != 0,
+                              L, sc);
+        } else {
+            dprun_block<false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp, vec_ok != 0,
+                               L, StoreClass<2>{});
+        }
     }
 }
 
@@ -546,19 +676,20 @@ hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int
 template <class TS>
 static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits, int64_t m,
                                       int64_t n, int64_t ldw, ScratchHeader *hdr,
-                                      int32_t *serial_state, uint8_t *sat, ms_square *out) {
+                                      int32_t *serial_state, uint8_t *sat, int32_t *bounds,
+                                      ms_square *out) {
     const int64_t ntx = cdiv(cdiv(n, 64), TS::OWN_WORDS);
     const int64_t ntiles = cdiv(m, TS::TR) * ntx;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 4),
                                                                    (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_probe<TS>, dim3((unsigned)blocks), dim3(256), 0, env.stream, bits,
-                       m, n, ldw, ntiles, ntx, hdr, sat);
+                       m, n, ldw, ntiles, ntx, hdr, sat, bounds);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t rblocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 8),
                                                                     (int64_t)env.num_cus * 2));
     hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks), dim3(256), 0, env.stream,
-                       bits, m, n, ldw, ntiles, ntx, hdr, sat, serial_state, out);
+                       bits, m, n, ldw, ntiles, ntx, hdr, sat, bounds, serial_state, out);
     return hipGetLastError();
 }
 
@@ -570,39 +701,46 @@ int64_t max_probe_tiles(int64_t m, int64_t n) {
 
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, ms_square *out) {
+                             uint8_t *sat, int32_t *bounds, ms_square *out) {
     switch (variant) {
-    case 0: return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, out);
-    case 1: return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, out);
-    default: return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, out);
+    case 0: return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds, out);
+    case 1: return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds, out);
+    default: return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds, out);
     }
 }
 
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
-                             int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state) {
+                             int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state,
+                             const MapRegions *regions) {
     const int vec_ok = ((uintptr_t)dp % 16 == 0) && (ld_dp % 4 == 0);
     const int64_t items_bound = cdiv(m, 16) * cdiv(n, 64);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(items_bound, 4),
                                                                    (int64_t)env.num_cus * 8));
     const dim3 g((unsigned)blocks), b(256);
+    const int32_t *bounds = regions ? regions->bounds : nullptr;
+    const int64_t trows = regions ? regions->tile_rows : 1;
+    const int64_t tntx = regions ? regions->tile_ntx : 1;
     // narrow kernel: squares up to 448 (8 x 64 - 64); window 512 columns, 1 or 2 groups
-    constexpr int64_t NARROW_REACH = 448;
+    constexpr int64_t NARROW_REACH = msk::MAP_NARROW_REACH;
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
-                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0);
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0,
+                           bounds, trows, tntx);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
-                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0);
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0,
+                           bounds, trows, tntx);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // a square wider than the narrow kernel's reach can only exist when both sides exceed it
     if (std::min(m, n) > NARROW_REACH) {
-        // one block per CU: cheap to retire when idle, and wide squares make few, long items
-        const dim3 gw((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, env.num_cus)));
-        hipLaunchKernelGGL((msk::k_dpmap<8, 4>), gw, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
-                           maxsq, (int64_t)band_rows, serial_state, vec_ok, NARROW_REACH, 1);
+        // three 48 KB blocks fit a CU
+        const dim3 gw((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks,
+                                                                        (int64_t)env.num_cus * 3)));
+        hipLaunchKernelGGL(msk::k_dpmap_wide, gw, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx);
         e = hipGetLastError();
     }
     return e;

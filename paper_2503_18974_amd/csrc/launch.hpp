@@ -45,13 +45,22 @@ hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int
 // one byte per probe tile (max_probe_tiles(m, n) bytes cover every variant).
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, ms_square *out);
+                             uint8_t *sat, int32_t *bounds, ms_square *out);
 int64_t max_probe_tiles(int64_t m, int64_t n);
 
-// dp map of one matrix; reads S from *maxsq on the device (a largest-square result).
+// Per-tile bounds of the search that ran in the same call, for a map split by tile class.
+struct MapRegions {
+    const int32_t *bounds;     // one per probe tile: an upper bound on its largest side, or -1
+    int64_t tile_rows;         // the probe variant's owned rows per tile
+    int64_t tile_ntx;          // tiles per tile row
+};
+
+// dp map of one matrix; reads S from *maxsq on the device (a largest-square result).  With
+// `regions`, the halos follow the per-tile bounds (see k_dpmap).
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
-                             int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state);
+                             int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state,
+                             const MapRegions *regions = nullptr);
 
 // Write a constant result (empty matrices).
 hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,

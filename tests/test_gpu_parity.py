@@ -212,3 +212,39 @@ def test_resolve_falls_back_to_serial(dev):
     pass finishes the matrix."""
     announce("serial fallback 3300")
     assert_same(np.ones((3300, 3300), np.uint8), dev)
+
+
+@pytest.mark.parametrize("side", [300, 449, 700, 1500, 2100])
+def test_map_from_max_wide(dev, side):
+    """The map from an earlier search's device result (no per-tile bounds): the 2048-column
+    block kernel for 448 < S <= 1984, the one-wave sweep beyond, the narrow kernel below."""
+    import torch
+    announce("map_from_max", side)
+    rng = np.random.default_rng([side, 11])
+    m, n = side + 260, side + 410
+    a = (rng.random((m, n)) < 0.7).astype(np.uint8)
+    r0, c0 = int(rng.integers(0, m - side)), int(rng.integers(0, n - side))
+    a[r0:r0 + side, c0:c0 + side] = 1
+    d = to_dev_bits(oracle.pack(a), dev)
+    res = M.max_square(d, n, sync=False)
+    dp = torch.full((m, n), -7, dtype=torch.int32, device=dev)
+    M.square_map_from_max(d, n, res, dp=dp)
+    ref_dp, ref = oracle.square_map(a)
+    assert tuple(res.cpu().tolist()) == ref
+    np.testing.assert_array_equal(dp.cpu().numpy(), ref_dp)
+
+
+@pytest.mark.parametrize("spots", [1, 3])
+def test_map_regions_mixed(dev, spots):
+    """Several wide squares in small-square noise: the map splits tiles by their search bound
+    (wide halos only around the big squares), so seams between the classes must agree."""
+    announce("map_regions", spots)
+    rng = np.random.default_rng([spots, 12])
+    m, n = 1800, 5200
+    a = (rng.random((m, n)) < 0.8).astype(np.uint8)
+    sides = [900, 520, 470][:spots]
+    for k, s in enumerate(sides):
+        r0 = int(rng.integers(0, m - s))
+        c0 = 1700 * k + int(rng.integers(0, 1700 - s))
+        a[r0:r0 + s, c0:c0 + s] = 1
+    assert_same(a, dev)
