@@ -164,6 +164,25 @@ ms_status ms_all_max_squares(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int
                              int64_t capacity, int64_t *d_count, void *d_workspace,
                              size_t workspace_bytes, void *stream);
 
+/*
+ * Largest all-ones rectangle: the extension to maximal rectangles that the paper proposes as
+ * future work (Section 6), in the histogram form of its related work (Section 2.3): with
+ * H[i][j] the height of the run of ones ending at (i, j), the widest rectangle of height h
+ * whose bottom row is i spans the longest run of columns with H[i][j] >= h.
+ * Writes one ms_rect to d_out (device or pinned host memory): the largest area; among the
+ * rectangles reaching it, the bottom-right corner (row, col) first in row-major order, then
+ * the smallest height; height x width = area.  An empty or all-zero matrix gives
+ * {0, -1, -1, 0, 0}.  Rows up to 32768 columns (ceil(n / 64) <= 512 words); wider rows give
+ * MS_ERR_UNSUPPORTED.  Uses the context's scratch (one header and a record per wave, allocated
+ * on first use).
+ * Invalid: as ms_max_square.
+ */
+typedef struct {
+    int64_t area, row, col, height, width;
+} ms_rect;
+ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                           int64_t ld_words, ms_rect *d_out, void *stream);
+
 /* Autotuning.  ms_num_candidates / ms_candidate enumerate the launch shapes this build can
  * run; ms_set_config forces one (NULL restores tuned/default choices); ms_get_config reports
  * the shape that would be used for an m x n matrix.  ms_autotune times every candidate on the

@@ -5,9 +5,10 @@ this package.  The product (the HIP library and its binding) never calls it, and
 calls the product: the two share no code.
 
 The arithmetic lives in plain C (``oracle.c``: the dp recurrence of Section 2.1 eq. (1) in
-full-table and rolling-row form, its own bit unpacker/packer, and the paper's Algorithm 1 as
-a second witness); this module only marshals numpy arrays through ctypes and builds the
-shared object with gcc when it is missing.
+full-table and rolling-row form, its own bit unpacker/packer, the paper's Algorithm 1 as a
+second witness, and the largest all-ones rectangle by its plain definition); this module only
+marshals numpy arrays through ctypes and builds the shared object with gcc when it is
+missing.
 """
 from __future__ import annotations
 
@@ -51,6 +52,8 @@ def lib():
             "oracle_unpack": [_p, _i64, _i64, _i64, _p, _i64],
             "oracle_freq_alg1_u8": [_p, _i64, _i64, _i64, _p, _p],
             "oracle_all_masks": [ctypes.c_int, ctypes.c_int, _p, _p],
+            "oracle_max_rect_u8": [_p, _i64, _i64, _i64, _p],
+            "oracle_max_rect_packed": [_p, _i64, _i64, _i64, _p],
             "oracle_stream_next": [_p, _i64, _p, _i64],
             "oracle_stream_result": [_p, _p],
             "oracle_stream_close": [_p],
@@ -185,3 +188,23 @@ def all_masks(m: int, n: int):
     corner = np.zeros(cnt, np.int64)
     _check(lib().oracle_all_masks(m, n, _ptr(side), _ptr(corner)))
     return side, corner
+
+
+def max_rect(a) -> tuple[int, int, int, int, int]:
+    """Largest all-ones rectangle of a uint8/bool (m, n) array: (area, row, col, height, width)
+    with (row, col) its bottom-right corner, first in row-major order among the largest, then
+    the smallest height; (0, -1, -1, 0, 0) when there is none."""
+    a = _u8(a)
+    m, n = a.shape
+    res = np.zeros(5, np.int64)
+    _check(lib().oracle_max_rect_u8(_ptr(a), m, n, max(n, 1), _ptr(res)))
+    return tuple(int(x) for x in res)
+
+
+def max_rect_packed(bits: np.ndarray, n: int) -> tuple[int, int, int, int, int]:
+    """As max_rect, from packed uint64 rows (column j = bit j & 63 of word j >> 6)."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    m = bits.shape[0]
+    res = np.zeros(5, np.int64)
+    _check(lib().oracle_max_rect_packed(_ptr(bits), m, n, max(bits.shape[1], 1), _ptr(res)))
+    return tuple(int(x) for x in res)

@@ -75,3 +75,73 @@ def all_masks(m: int, n: int):
         side[has] = s
         corner[has] = first[has]
     return side, corner
+
+
+# ---- largest all-ones rectangle (the future-work extension of Section 6) ----
+
+def max_rect(a: np.ndarray) -> tuple[int, int, int, int, int]:
+    """Every rectangle checked cell by cell through a 2-D prefix sum.  Returns (area, row, col,
+    height, width): the largest area; among rectangles reaching it, the bottom-right corner
+    first in row-major order, then the smallest height; (0, -1, -1, 0, 0) when none."""
+    a = (np.asarray(a) != 0).astype(np.int64)
+    m, n = a.shape
+    P = np.zeros((m + 1, n + 1), np.int64)
+    P[1:, 1:] = a.cumsum(0).cumsum(1)
+    best = (0, -1, -1, 0, 0)
+    for i in range(m):
+        for j in range(n):
+            for h in range(1, i + 2):
+                for w in range(j + 1, 0, -1):
+                    ones = P[i + 1, j + 1] - P[i + 1 - h, j + 1] - P[i + 1, j + 1 - w] \
+                        + P[i + 1 - h, j + 1 - w]
+                    if ones == h * w:
+                        if h * w > best[0]:
+                            best = (h * w, i, j, h, w)
+                        break
+    return best
+
+
+def rect_all_masks(m: int, n: int) -> np.ndarray:
+    """Exhaustive over every m x n 0/1 matrix (A[i][j] = bit i*n + j of the mask): an array
+    (2^(m*n), 5) of (area, row, col, height, width) as max_rect defines them."""
+    cnt = 1 << (m * n)
+    masks = np.arange(cnt, dtype=np.uint32)
+    A = np.zeros((cnt, m, n), np.int64)
+    for i in range(m):
+        for j in range(n):
+            A[:, i, j] = (masks >> (i * n + j)) & 1
+    P = np.zeros((cnt, m + 1, n + 1), np.int64)
+    P[:, 1:, 1:] = A.cumsum(1).cumsum(2)
+    out = np.zeros((cnt, 5), np.int64)
+    out[:, 1:3] = -1
+    for i in range(m):
+        for j in range(n):
+            for h in range(1, i + 2):
+                for w in range(j + 1, 0, -1):
+                    ones = P[:, i + 1, j + 1] - P[:, i + 1 - h, j + 1] \
+                        - P[:, i + 1, j + 1 - w] + P[:, i + 1 - h, j + 1 - w]
+                    hit = (ones == h * w) & (h * w > out[:, 0])
+                    out[hit] = (h * w, i, j, h, w)
+    return out
+
+
+def rect_area_histogram_stack(a: np.ndarray) -> int:
+    """Largest all-ones rectangle area by the histogram method the paper's related work
+    describes (Section 2.3): per row, the heights of the runs of ones ending there, and the
+    textbook stack pass for the largest rectangle under a histogram."""
+    a = np.asarray(a) != 0
+    m, n = a.shape
+    heights = [0] * n
+    best = 0
+    for i in range(m):
+        for j in range(n):
+            heights[j] = heights[j] + 1 if a[i, j] else 0
+        stack = []  # column indices with increasing heights
+        for j in range(n + 1):
+            cur = heights[j] if j < n else 0
+            while stack and heights[stack[-1]] >= cur:
+                top = stack.pop()
+                left = stack[-1] + 1 if stack else 0
+                best = max(best, heights[top] * (j - left))
+            stack.append(j)
+    return best

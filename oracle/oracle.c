@@ -21,6 +21,9 @@
  * Also here, as a second witness: the paper's frequency-based Algorithm 1 as written
  * (Section 3), with a record of where found_max_width is incremented.
  *
+ * And the largest all-ones rectangle (the extension of Section 6's future work, in the
+ * histogram form of Section 2.3), by its plain definition; see max_rect below.
+ *
  * Inputs: uint8 row-major (a cell is 1 iff its byte is non-zero), or packed uint64 rows where
  * column j is bit (j & 63) of word (j >> 6), padding bits ignored.
  */
@@ -328,4 +331,76 @@ int oracle_all_masks(int m, int n, int64_t *side, int64_t *corner) {
         corner[mask] = at;
     }
     return ORACLE_OK;
+}
+
+/*
+ * ---- largest all-ones rectangle ----
+ * The extension the paper lists in its future work (Section 6), in the formulation its related
+ * work describes (Section 2.3): each row becomes a histogram of the heights of the runs of ones
+ * ending in it, H[i][j] = A[i][j] ? H[i-1][j] + 1 : 0.
+ *
+ * Plain definition.  A rectangle is rows i-h+1..i and columns j-w+1..j, all ones; its area is
+ * h * w.  For bottom-right corner (i, j) and height h the widest such rectangle has
+ * w = W_h(i, j), the number of consecutive columns ending at j whose height in row i is at least
+ * h; so the largest area is the maximum of h * W_h(i, j) over every cell (i, j) and every
+ * 1 <= h <= H[i][j].  Reported: that area; among the rectangles reaching it, the bottom-right
+ * corner first in row-major order, then the smallest height.  res = {area, row, col, height,
+ * width}; an empty or all-zero matrix gives {0, -1, -1, 0, 0}.
+ *
+ * Evaluation: rows top to bottom; per row, columns left to right, keeping W_h for every h up to
+ * the row's tallest height; candidates are visited in (row, col, height) order and only a
+ * strictly larger area replaces the best, which yields the tie-break above.
+ */
+static int max_rect(const reader *r, int64_t m, int64_t n, int64_t res[5]) {
+    res[0] = 0;
+    res[1] = -1;
+    res[2] = -1;
+    res[3] = 0;
+    res[4] = 0;
+    if (m == 0 || n == 0) return ORACLE_OK;
+    int64_t *H = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int64_t *W = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t)); /* W[h], h = 1..m */
+    if (!H || !W) {
+        free(H);
+        free(W);
+        return ORACLE_ENOMEM;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t hmax = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            H[j] = cell(r, i, j) ? H[j] + 1 : 0;
+            if (H[j] > hmax) hmax = H[j];
+        }
+        for (int64_t h = 1; h <= hmax; ++h) W[h] = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            for (int64_t h = 1; h <= hmax; ++h) {
+                W[h] = H[j] >= h ? W[h] + 1 : 0;
+                if (h <= H[j] && h * W[h] > res[0]) {
+                    res[0] = h * W[h];
+                    res[1] = i;
+                    res[2] = j;
+                    res[3] = h;
+                    res[4] = W[h];
+                }
+            }
+        }
+    }
+    free(H);
+    free(W);
+    return ORACLE_OK;
+}
+
+int oracle_max_rect_u8(const uint8_t *a, int64_t m, int64_t n, int64_t ld, int64_t res[5]) {
+    int rc = check_dims(m, n, ld, n, a);
+    if (rc) return rc;
+    reader r = {a, NULL, ld};
+    return max_rect(&r, m, n, res);
+}
+
+int oracle_max_rect_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t ld_words,
+                           int64_t res[5]) {
+    int rc = check_dims(m, n, ld_words, (n + 63) / 64, bits);
+    if (rc) return rc;
+    reader r = {NULL, bits, ld_words};
+    return max_rect(&r, m, n, res);
 }

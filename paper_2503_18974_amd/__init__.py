@@ -26,6 +26,7 @@ __all__ = [
     "ms_set_config", "ms_get_config", "ms_candidate", "ms_num_candidates", "ms_autotune",
     "ms_autotune_save", "ms_autotune_load", "Context", "pack_u8", "max_square", "square_map",
     "max_square_batched", "square_map_from_max", "area", "words_per_row",
+    "Rect", "ms_max_rectangle", "max_rectangle",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,6 +68,16 @@ class Square:
         return self.side * self.side
 
 
+@dataclass(frozen=True)
+class Rect:
+    """Largest all-ones rectangle: area, bottom-right corner (row, col), height and width."""
+    area: int
+    row: int
+    col: int
+    height: int
+    width: int
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -101,6 +112,7 @@ def lib():
             "ms_all_max_squares_workspace_size": [_P, _I64, _I64, ctypes.POINTER(ctypes.c_size_t)],
             "ms_all_max_squares": [_P, _P, _I64, _I64, _I64, _P, _P, _I64, _P, _P,
                                    ctypes.c_size_t, _P],
+            "ms_max_rectangle": [_P, _P, _I64, _I64, _I64, _P, _P],
             "ms_autotune_save": [_P, ctypes.c_char_p],
             "ms_autotune_load": [_P, ctypes.c_char_p],
         }
@@ -324,6 +336,24 @@ def square_map_from_max(bits, n: int, result, ctx=None, stream=None, dp=None):
                                   dp.stride(0) if dp.numel() else max(n, 1), _stream(stream)),
            "ms_square_map_from_max")
     return dp
+
+
+def ms_max_rectangle(ctx, d_bits, m, n, ld_words, d_out, stream) -> int:
+    return lib().ms_max_rectangle(ctx, d_bits, m, n, ld_words, d_out, stream)
+
+
+def max_rectangle(bits, n: int, ctx=None, stream=None, out=None, sync: bool = True):
+    """Largest all-ones rectangle of a packed (m, >= ceil(n/64)) int64 CUDA tensor.  Returns a
+    Rect when sync, else the int64 (5,) device tensor (area, row, col, height, width)."""
+    torch = _torch()
+    _check_bits(bits, n)
+    m = bits.size(0)
+    res = torch.empty(5, dtype=torch.int64, device=bits.device) if out is None else out
+    _check(ms_max_rectangle(_ctx(ctx), bits.data_ptr(), m, n, _ld_words(bits, n), res.data_ptr(),
+                            _stream(stream)), "ms_max_rectangle")
+    if not sync:
+        return res
+    return Rect(*(int(x) for x in res.cpu().tolist()))
 
 
 def all_max_squares(bits, n: int, result=None, capacity: int | None = None, ctx=None,

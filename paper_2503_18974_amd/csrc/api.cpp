@@ -71,6 +71,9 @@ struct ms_ctx {
     std::map<int, ms_config> tuned;
     std::vector<GraphEntry> graphs;
     hipStream_t capture_stream = nullptr;
+    // largest-rectangle scratch: header | one record per wave of the launch
+    void *rect_scratch = nullptr;
+    bool rect_dirty = false;
     std::mutex mu;
 };
 
@@ -266,13 +269,14 @@ ms_status ms_destroy(ms_ctx *ctx) {
         for (auto &kv : g_default)
             if (kv.second == ctx) return MS_ERR_INVALID_ARGUMENT;  // default contexts live on
     }
-    if (ctx->scratch || !ctx->graphs.empty()) {
+    if (ctx->scratch || ctx->rect_scratch || !ctx->graphs.empty()) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->rect_scratch) (void)hipFree(ctx->rect_scratch);
     delete ctx;
     return MS_OK;
 }
@@ -434,6 +438,42 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
     }
     c->graphs.push_back(GraphEntry{d_mats, count, d_out, d_workspace, variant, sh, exec});
     return hip_status(hipGraphLaunch(exec, st));
+}
+
+ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                           int64_t ld_words, ms_rect *d_out, void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (!d_out) return MS_ERR_INVALID_ARGUMENT;
+    if (cdiv(n, 64) > mshost::RECT_MAX_WORDS) return MS_ERR_UNSUPPORTED;
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    if (!c->rect_scratch) {
+        const size_t bytes = sizeof(mshost::RectScratch) +
+                             (size_t)mshost::rect_max_waves(c->num_cus) * sizeof(mshost::RectRecord);
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return hip_status(e);
+        if (hipMemset(p, 0, sizeof(mshost::RectScratch)) != hipSuccess) {
+            (void)hipFree(p);
+            return MS_ERR_HIP;
+        }
+        c->rect_scratch = p;
+    } else if (c->rect_dirty) {
+        if (hipMemsetAsync(c->rect_scratch, 0, sizeof(mshost::RectScratch), st) != hipSuccess)
+            return MS_ERR_HIP;
+    }
+    c->rect_dirty = false;
+    mshost::LaunchEnv env{c->num_cus, st};
+    hipError_t e = mshost::launch_max_rect(env, d_bits, m, n, ld_words,
+                                           static_cast<mshost::RectScratch *>(c->rect_scratch),
+                                           d_out);
+    if (e != hipSuccess) c->rect_dirty = true;
+    return hip_status(e);
 }
 
 ms_status ms_all_max_squares_workspace_size(ms_ctx *ctx, int64_t m, int64_t n, size_t *bytes) {

@@ -86,4 +86,24 @@ hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m,
                           int64_t ldw, const ms_square *maxsq, int64_t *pos, int64_t capacity,
                           int64_t *count, void *ws);
 
+
+// Largest all-ones rectangle (rect.hip).  The scratch is a header followed by one record per
+// wave of the launch (rect_max_waves records); the header returns to zero at the end of every
+// call, so it needs clearing only when allocated.
+struct RectScratch {
+    unsigned long long best_area;  // largest area any finished row has reached (pruning bound)
+    uint32_t done;                 // waves that have written their record
+    uint32_t pad0;
+    uint64_t pad1[6];
+};
+static_assert(sizeof(RectScratch) == 64, "rect header layout");
+struct RectRecord {
+    int64_t area, pos, height;     // a wave's best: area, i * n + col of its corner, height
+};
+constexpr int RECT_BLOCKS_PER_CU = 8;
+constexpr int64_t RECT_MAX_WORDS = 512;  // widest row: 64 lanes x 8 words (32768 columns)
+int64_t rect_max_waves(int num_cus);
+hipError_t launch_max_rect(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
+                           int64_t ldw, RectScratch *rs, ms_rect *out);
+
 } // namespace mshost

@@ -145,3 +145,19 @@ def test_all_max_squares_workspace():
     assert 0 < size.value < big
     # a workspace below the required size is refused before any device work
     assert L.ms_all_max_squares(None, P, 1000, 2000, 32, P, P, 4, P, P, 16, None) == 2
+
+
+@pytest.mark.parametrize("args", [
+    (None, None, -1, 5, 1, P, None),          # negative m
+    (None, None, 5, 5, 1, P, None),           # null bits with cells
+    (None, P, 5, 130, 2, P, None),            # ld_words < ceil(n/64)
+    (None, P, 5, 5, 1, None, None),           # null result
+    (None, P, 1 << 22, 1 << 22, 1 << 16, P, None),  # m*n beyond the 2^44 key range
+])
+def test_max_rectangle_invalid(args):
+    assert M.lib().ms_max_rectangle(*args) == INVALID
+
+
+def test_max_rectangle_too_wide_is_unsupported():
+    """Rows wider than 512 words are refused before any device work."""
+    assert M.lib().ms_max_rectangle(None, P, 4, 32769, 513, P, None) == 5
