@@ -3,6 +3,10 @@ workload, plus a sha256 of the packed input so a consumer can confirm it regener
 same bits.  Calls only the oracle and the input generators.
 
     python tests/golden/make_golden.py [--only c1,c2,c3a,c3b,c3c,c4]
+    python tests/golden/make_golden.py --rect [--only c1,c2,c3a,c3c]
+
+--rect adds, to the existing records, the oracle's largest all-ones rectangle as
+"rect": [area, row, col, height, width] (rows of at most 32768 columns only).
 
 The batched workload's 10000 results go to c4_results.txt instead (one line per matrix).
 """
@@ -57,12 +61,45 @@ def write_c4(count=10000):
     print("c4", count, "matrices, %.1fs" % (time.time() - t), flush=True)
 
 
+def add_rects(data, want):
+    """The oracle's largest rectangle for each wanted record (input regenerated and checked
+    against the stored sha256 first)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(rec, bits):
+        if sha(bits) != rec["sha256_packed"]:
+            raise SystemExit("regenerated input differs from the recorded one")
+        t = time.time()
+        rec["rect"] = list(oracle.max_rect_packed(bits, rec["n"]))
+        print(rec["m"], rec["n"], rec.get("p"), rec["rect"], "%.1fs" % (time.time() - t),
+              flush=True)
+
+    if "c1" in want:
+        one(data["c1"], W.pack_rows(W.c1()))
+    if "c2" in want:
+        jobs = [(data["c2"]["%d_%d" % (n, d)], (n, p, seed)) for n, d, p, seed in W.paper_grid()]
+        with ThreadPoolExecutor(6) as ex:   # the oracle's C call releases the GIL
+            list(ex.map(lambda j: one(j[0], W.gen_bernoulli_packed(j[1][0], j[1][0], j[1][1],
+                                                                   j[1][2])), jobs))
+    for name in ("c3a", "c3c"):
+        if name in want:
+            bits, m, n, _ = W.large_packed(name)
+            one(data[name], bits)
+            del bits
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", default="c1,c2,c3a,c3b,c3c")
+    ap.add_argument("--rect", action="store_true")
     args = ap.parse_args()
     want = set(args.only.split(","))
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    if args.rect:
+        add_rects(data, want)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        return
     data["_note"] = ("Written by tests/golden/make_golden.py from the oracle only. "
                      "side/row/col: largest all-ones square and its row-major-first bottom-right corner.")
     if "c1" in want:

@@ -1,5 +1,6 @@
 """Full-size parity on the large single matrices: side and corner against the stored oracle
-values, and every cell of the int32 map against the rolling-row oracle, chunk by chunk."""
+values, every cell of the int32 map against the rolling-row oracle, chunk by chunk, and the
+largest rectangle against the stored oracle value where the rows fit its kernel."""
 import hashlib
 import json
 import os
@@ -60,6 +61,13 @@ def test_large_config(dev, name):
                 r0 + bad[0], bad[1], got[tuple(bad)], ref[tuple(bad)]))
     assert st.result() == (g["side"], g["row"], g["col"])
     announce("large", name, "map verified in %.1fs" % (time.time() - t3))
+    del dp
+    # the largest rectangle against the oracle's stored value (rows up to 32768 columns)
+    if "rect" in g:
+        t4 = time.time()
+        r = M.max_rectangle(d, n)
+        announce("large", name, "max_rectangle %s in %.3fs" % (r, time.time() - t4))
+        assert [r.area, r.row, r.col, r.height, r.width] == g["rect"]
 
 
 def test_c4_batched_full(dev):
