@@ -187,6 +187,13 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
             H[g][t] = 0;
             D[g][t] = 0;
         }
+    // tile row of the current row relative to ty0, and the row's offset in its tile row,
+    // advanced per row (no division in the row loop)
+    int64_t kq = 0, kr = 0;
+    if (CLASSED) {
+        kq = uniform(rh / sc.tile_rows - sc.ty0);
+        kr = uniform(rh % sc.tile_rows);
+    }
 
     for (int64_t r0 = rh; r0 < rb; r0 += rc_max) {
         const int rc = (int)(rb - r0 < rc_max ? rb - r0 : rc_max);
@@ -246,7 +253,11 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                 }
             }
             int32_t dleft_old = 0;  // previous-row dp just left of the group
-            const int krow = (CLASSED && own_row) ? (int)(i / sc.tile_rows - sc.ty0) : 0;
+            const int krow = (CLASSED && own_row) ? (int)kq : 0;
+            if (CLASSED && ++kr == sc.tile_rows) {
+                kr = 0;
+                ++kq;
+            }
 #pragma unroll
             for (int g = 0; g < NGMAX; ++g) {
                 if (g < ng) {
@@ -895,6 +906,12 @@ __device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int6
             D[g][t] = 0;
         }
     if (tid < 8) L.slot[tid] = 0;   // zero state left of every wave before the first row
+    // tile row of the current row relative to ty0 and the row's offset in it (see dprun)
+    int64_t kq = 0, kr = 0;
+    if (CLASSED) {
+        kq = uniform(rh / sc.tile_rows - sc.ty0);
+        kr = uniform(rh % sc.tile_rows);
+    }
 
     for (int64_t r0 = rh; r0 < rb; r0 += rc_max) {
         const int rc = (int)(rb - r0 < rc_max ? rb - r0 : rc_max);
@@ -929,7 +946,11 @@ __device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int6
             const int par = (int)(i & 1);
             // previous-row dp just left of this wave's first group (from wave wv - 1)
             int32_t dleft_old = wv > 0 ? L.slot[par * 4 + wv - 1] : 0;
-            const int krow = (CLASSED && own_row) ? (int)(i / sc.tile_rows - sc.ty0) : 0;
+            const int krow = (CLASSED && own_row) ? (int)kq : 0;
+            if (CLASSED && ++kr == sc.tile_rows) {
+                kr = 0;
+                ++kq;
+            }
 #pragma unroll
             for (int gl = 0; gl < GPW; ++gl) {
                 const int g = wv * GPW + gl;

@@ -212,7 +212,8 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
                                                int64_t band_rows, int32_t *serial_state,
                                                int vec_ok, int64_t s_lo, int serial_beyond,
                                                const int32_t *__restrict__ bounds,
-                                               int64_t tile_rows, int64_t tile_ntx) {
+                                               int64_t tile_rows, int64_t tile_ntx,
+                                               int64_t min_items) {
     constexpr int64_t GW = 64 * CPL;
     constexpr int64_t WIN = NGMAX * GW;
     constexpr int64_t REACH = WIN - 64;   // largest S whose halo leaves a 64-column output
@@ -239,13 +240,20 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
     }
     int64_t ng = (hc + (4 * hc > 256 ? 4 * hc : 256) + GW - 1) / GW;
     ng = ng < 1 ? 1 : (ng > NGMAX ? NGMAX : ng);
+    const int64_t rmin = 2 * Sg > 16 ? 2 * Sg : 16;
+    // where even the shortest bands leave fewer items than min_items (a small matrix: each
+    // wave's sequence of rows is the latency), a window one group narrower halves every row's
+    // work, as long as it still leaves a 64-column output
+    if (ng > 1 && (ng - 1) * GW >= hc + 64 &&
+        ((m + rmin - 1) / rmin) * ((n + ng * GW - hc - 1) / (ng * GW - hc)) < min_items)
+        ng -= 1;
     const int64_t ow = ng * GW - hc;
     const int64_t nwin = (n + ow - 1) / ow;
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    // the tallest bands (the least halo work) that still leave min_items items
     int64_t R = band_rows > 4 * Sg ? band_rows : 4 * Sg;
-    const int64_t rmin = 2 * Sg > 16 ? 2 * Sg : 16;
-    while (R > rmin && ((m + R - 1) / R) * nwin < nwave) R = (R / 2 > rmin) ? R / 2 : rmin;
+    while (R > rmin && ((m + R - 1) / R) * nwin < min_items) R = (R / 2 > rmin) ? R / 2 : rmin;
     if (region) {
         // the wide pass touches few items: short bands spread them over more waves; either pass
         // keeps an item within 32 tile rows (one mask bit per tile row)
@@ -721,16 +729,17 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
     const int32_t *bounds = regions ? regions->bounds : nullptr;
     const int64_t trows = regions ? regions->tile_rows : 1;
     const int64_t tntx = regions ? regions->tile_ntx : 1;
+    const int64_t min_items = (int64_t)env.num_cus * 4 * MAP_ITEMS_PER_SIMD;
     // narrow kernel: squares up to 448 (8 x 64 - 64); window 512 columns, 1 or 2 groups
     constexpr int64_t NARROW_REACH = msk::MAP_NARROW_REACH;
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0,
-                           bounds, trows, tntx);
+                           bounds, trows, tntx, min_items);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0,
-                           bounds, trows, tntx);
+                           bounds, trows, tntx, min_items);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
