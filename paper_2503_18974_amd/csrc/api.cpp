@@ -71,7 +71,7 @@ struct ms_ctx {
     std::map<int, ms_config> tuned;
     std::vector<GraphEntry> graphs;
     hipStream_t capture_stream = nullptr;
-    // largest-rectangle scratch: header | one record per wave of the launch
+    // largest-rectangle scratch: header | one record per block of the launch
     void *rect_scratch = nullptr;
     bool rect_dirty = false;
     std::mutex mu;
@@ -454,7 +454,7 @@ ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64
     hipStream_t st = (hipStream_t)stream;
     if (!c->rect_scratch) {
         const size_t bytes = sizeof(mshost::RectScratch) +
-                             (size_t)mshost::rect_max_waves(c->num_cus) * sizeof(mshost::RectRecord);
+                             (size_t)mshost::rect_max_blocks(c->num_cus) * sizeof(mshost::RectRecord);
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) return hip_status(e);

@@ -576,12 +576,43 @@ __global__ __launch_bounds__(256) void k_allmax_count(const uint64_t *__restrict
     }
 }
 
-// One block: exclusive prefix of the counts in row-major (row, unit column) order, and the
-// total (0 when S = 0; -1 when S is wider than the enumeration supports).
+// The exclusive prefix of the counts in row-major (row, unit column) order, in three passes over
+// chunks of SCAN_CHUNK consecutive entries: each block sums its chunk (k_allmax_chunks), one block
+// scans the chunk sums and writes the total (k_allmax_scan: 0 when S = 0, -1 when S is wider than
+// the enumeration supports), and each block scans its chunk from the chunk's prefix
+// (k_allmax_offsets).  Every pass reads its chunk with consecutive threads on consecutive words.
+constexpr int SCAN_PER_THREAD = 16;
+constexpr int64_t SCAN_CHUNK = 256 * SCAN_PER_THREAD;
+
+__global__ __launch_bounds__(256) void k_allmax_chunks(const ms_square *__restrict__ maxsq,
+                                                       const uint32_t *__restrict__ counts,
+                                                       int64_t entries,
+                                                       uint64_t *__restrict__ chunk_sums) {
+    const int64_t S = uniform(maxsq->side);
+    if (S <= 0 || S > ALL_MAX_SIDE) return;
+    __shared__ uint64_t wsum[4];
+    const int64_t nchunks = (entries + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t base = c * SCAN_CHUNK;
+        uint64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            const int64_t e = base + (int64_t)k * 256 + threadIdx.x;
+            if (e < entries) sum += counts[e];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (__lane_id() == 0) wsum[threadIdx.x / WAVE] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) chunk_sums[c] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+}
+
+// One block: exclusive prefix of the chunk sums (in place) and the total.
 __global__ __launch_bounds__(1024) void k_allmax_scan(const ms_square *__restrict__ maxsq,
-                                                      const uint32_t *__restrict__ counts,
-                                                      int64_t entries,
-                                                      uint64_t *__restrict__ offsets,
+                                                      uint64_t *__restrict__ chunk_sums,
+                                                      int64_t nchunks,
                                                       int64_t *__restrict__ total_out) {
     __shared__ uint64_t part[1024];
     const int64_t S = maxsq->side;
@@ -590,11 +621,11 @@ __global__ __launch_bounds__(1024) void k_allmax_scan(const ms_square *__restric
         if (tid == 0) *total_out = S <= 0 ? 0 : -1;
         return;
     }
-    const int64_t per = (entries + 1023) / 1024;
-    const int64_t lo = tid * per < entries ? tid * per : entries;
-    const int64_t hi = lo + per < entries ? lo + per : entries;
+    const int64_t per = (nchunks + 1023) / 1024;
+    const int64_t lo = tid * per < nchunks ? tid * per : nchunks;
+    const int64_t hi = lo + per < nchunks ? lo + per : nchunks;
     uint64_t sum = 0;
-    for (int64_t e = lo; e < hi; ++e) sum += counts[e];
+    for (int64_t e = lo; e < hi; ++e) sum += chunk_sums[e];
     part[tid] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -605,10 +636,57 @@ __global__ __launch_bounds__(1024) void k_allmax_scan(const ms_square *__restric
     }
     uint64_t run = part[tid] - sum;
     for (int64_t e = lo; e < hi; ++e) {
-        offsets[e] = run;
-        run += counts[e];
+        const uint64_t c = chunk_sums[e];
+        chunk_sums[e] = run;
+        run += c;
     }
     if (tid == 1023) *total_out = (int64_t)part[1023];
+}
+
+// offsets[e] = the chunk's prefix + the counts before e within the chunk.
+__global__ __launch_bounds__(256) void k_allmax_offsets(const ms_square *__restrict__ maxsq,
+                                                        const uint32_t *__restrict__ counts,
+                                                        int64_t entries,
+                                                        const uint64_t *__restrict__ chunk_pre,
+                                                        uint64_t *__restrict__ offsets) {
+    const int64_t S = uniform(maxsq->side);
+    if (S <= 0 || S > ALL_MAX_SIDE) return;
+    __shared__ uint64_t carry[SCAN_PER_THREAD][4];
+    const int lane = __lane_id(), wv = threadIdx.x / WAVE;
+    const int64_t nchunks = (entries + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t base = c * SCAN_CHUNK;
+        // row k of the chunk: entries base + 256 k .. + 255, one per thread
+        uint32_t v[SCAN_PER_THREAD];
+        uint64_t incl[SCAN_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            const int64_t e = base + (int64_t)k * 256 + threadIdx.x;
+            v[k] = e < entries ? counts[e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            uint64_t x = v[k];
+#pragma unroll
+            for (int off = 1; off < WAVE; off <<= 1) {
+                const uint64_t y = __shfl_up(x, off);
+                if (lane >= off) x += y;
+            }
+            incl[k] = x;
+            if (lane == WAVE - 1) carry[k][wv] = x;
+        }
+        __syncthreads();
+        uint64_t run = chunk_pre[c];
+#pragma unroll
+        for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+            uint64_t before = run;
+            for (int w = 0; w < wv; ++w) before += carry[k][w];
+            const int64_t e = base + (int64_t)k * 256 + threadIdx.x;
+            if (e < entries) offsets[e] = before + incl[k] - v[k];
+            run += carry[k][0] + carry[k][1] + carry[k][2] + carry[k][3];
+        }
+        __syncthreads();
+    }
 }
 
 // The positions i * n + j of those cells, in row-major order, the first `capacity` of them.
@@ -843,7 +921,9 @@ AllMaxLayout all_max_layout(int64_t m, int64_t n) {
     L.entries = std::max<int64_t>(m, 0) * L.nux;
     L.counts = 0;
     L.offsets = align256(sizeof(uint32_t) * (size_t)L.entries);
-    L.total = L.offsets + align256(sizeof(uint64_t) * (size_t)(L.entries + 1));
+    L.chunks = L.offsets + align256(sizeof(uint64_t) * (size_t)(L.entries + 1));
+    L.total = L.chunks +
+              align256(sizeof(uint64_t) * (size_t)(cdiv(L.entries, msk::SCAN_CHUNK) + 1));
     return L;
 }
 
@@ -857,6 +937,10 @@ hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m,
     const AllMaxLayout L = all_max_layout(m, n);
     auto *counts = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + L.counts);
     auto *offsets = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + L.offsets);
+    auto *chunk_sums = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + L.chunks);
+    const int64_t nchunks = cdiv(L.entries, msk::SCAN_CHUNK);
+    const int64_t cblocks = std::max<int64_t>(1, std::min<int64_t>(nchunks,
+                                                                    (int64_t)env.num_cus * 8));
     const int64_t nunits = cdiv(m, (int64_t)msk::ALL_ROWS) * L.nux;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(nunits, 4),
                                                                    (int64_t)env.num_cus * 8));
@@ -864,8 +948,14 @@ hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m,
                        bits, m, n, ldw, maxsq, counts, L.nux, nunits);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(msk::k_allmax_scan, dim3(1), dim3(1024), 0, env.stream, maxsq, counts,
-                       L.entries, offsets, count);
+    hipLaunchKernelGGL(msk::k_allmax_chunks, dim3((unsigned)cblocks), dim3(256), 0, env.stream,
+                       maxsq, counts, L.entries, chunk_sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(msk::k_allmax_scan, dim3(1), dim3(1024), 0, env.stream, maxsq, chunk_sums,
+                       nchunks, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(msk::k_allmax_offsets, dim3((unsigned)cblocks), dim3(256), 0, env.stream,
+                       maxsq, counts, L.entries, chunk_sums, offsets);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(msk::k_allmax_write, dim3((unsigned)blocks), dim3(256), 0, env.stream,
                        bits, m, n, ldw, maxsq, offsets, L.nux, nunits, pos, capacity);

@@ -83,7 +83,7 @@ hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_
 // All maximal squares: workspace layout and launches.
 struct AllMaxLayout {
     int64_t nux, entries;
-    size_t counts, offsets, total;
+    size_t counts, offsets, chunks, total;  // byte offsets in the workspace, and its size
 };
 AllMaxLayout all_max_layout(int64_t m, int64_t n);
 hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
@@ -92,21 +92,19 @@ hipError_t launch_all_max(const LaunchEnv &env, const uint64_t *bits, int64_t m,
 
 
 // Largest all-ones rectangle (rect.hip).  The scratch is a header followed by one record per
-// wave of the launch (rect_max_waves records); the header returns to zero at the end of every
+// block of the launch (rect_max_blocks records); the header returns to zero at the end of every
 // call, so it needs clearing only when allocated.
 struct RectScratch {
     unsigned long long best_area;  // largest area any finished row has reached (pruning bound)
-    uint32_t done;                 // waves that have written their record
-    uint32_t pad0;
-    uint64_t pad1[6];
+    uint64_t pad[7];
 };
 static_assert(sizeof(RectScratch) == 64, "rect header layout");
 struct RectRecord {
-    int64_t area, pos, height;     // a wave's best: area, i * n + col of its corner, height
+    int64_t area, pos, height;     // a block's best: area, i * n + col of its corner, height
 };
 constexpr int RECT_BLOCKS_PER_CU = 8;
 constexpr int64_t RECT_MAX_WORDS = 512;  // widest row: 64 lanes x 8 words (32768 columns)
-int64_t rect_max_waves(int num_cus);
+int64_t rect_max_blocks(int num_cus);
 hipError_t launch_max_rect(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
                            int64_t ldw, RectScratch *rs, ms_rect *out);
 

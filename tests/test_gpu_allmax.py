@@ -84,3 +84,17 @@ def test_too_wide_reports_unsupported(dev):
     d = to_dev_bits(oracle.pack(np.ones((3100, 3100), np.uint8)), dev)
     with pytest.raises(M.MaxsqError):
         M.all_max_squares(d, 3100)
+
+
+def test_corners_spread_over_many_scan_chunks(dev):
+    """Equal squares planted down the whole matrix: the row-major prefix of the per-row counts
+    crosses many scan chunks (and the chunks' own prefix), so every carry is exercised."""
+    announce("allmax many chunks")
+    m, n = 9000, 4100
+    a = (np.random.default_rng(8).random((m, n)) < 0.3).astype(np.uint8)
+    for r0 in range(7, m - 30, 41):
+        for c0 in range(3 + (r0 % 5) * 61, n - 30, 397):
+            a[r0 - 1:r0 + 21, c0 - 1:c0 + 21] = 0
+            a[r0:r0 + 20, c0:c0 + 20] = 1
+    assert check(a, dev) > 2000
+    check(a, dev, capacity=1500)
