@@ -6,9 +6,9 @@ calls the product: the two share no code.
 
 The arithmetic lives in plain C (``oracle.c``: the dp recurrence of Section 2.1 eq. (1) in
 full-table and rolling-row form, its own bit unpacker/packer, the paper's Algorithm 1 as a
-second witness, and the largest all-ones rectangle by its plain definition); this module only
-marshals numpy arrays through ctypes and builds the shared object with gcc when it is
-missing.
+second witness, the largest all-ones rectangle by its plain definition, and the largest
+all-ones cube of a volume by the seven-neighbour recurrence); this module only marshals numpy
+arrays through ctypes and builds the shared object with gcc when it is missing.
 """
 from __future__ import annotations
 
@@ -54,6 +54,7 @@ def lib():
             "oracle_all_masks": [ctypes.c_int, ctypes.c_int, _p, _p],
             "oracle_max_rect_u8": [_p, _i64, _i64, _i64, _p],
             "oracle_max_rect_packed": [_p, _i64, _i64, _i64, _p],
+            "oracle_max_cube_packed": [_p, _i64, _i64, _i64, _i64, _p],
             "oracle_stream_next": [_p, _i64, _p, _i64],
             "oracle_stream_result": [_p, _p],
             "oracle_stream_close": [_p],
@@ -207,4 +208,33 @@ def max_rect_packed(bits: np.ndarray, n: int) -> tuple[int, int, int, int, int]:
     m = bits.shape[0]
     res = np.zeros(5, np.int64)
     _check(lib().oracle_max_rect_packed(_ptr(bits), m, n, max(bits.shape[1], 1), _ptr(res)))
+    return tuple(int(x) for x in res)
+
+
+def pack_volume(v) -> np.ndarray:
+    """uint8/bool (D, M, N) -> packed (D, M, ceil(N/64)) uint64, by the oracle's own packer."""
+    v = (np.asarray(v) != 0).astype(np.uint8)
+    D, M, N = v.shape
+    w = max((N + 63) // 64, 1)
+    out = np.zeros((D, M, w), np.uint64)
+    for z in range(D):
+        if M and N:
+            out[z] = pack(np.ascontiguousarray(v[z]))
+    return out
+
+
+def max_cube(v) -> tuple[int, int, int, int]:
+    """Largest all-ones cube of a (D, M, N) volume: (side, z, y, x) of its far corner, the first
+    in (z, y, x) order among the largest; (0, -1, -1, -1) when there is none."""
+    v = np.asarray(v)
+    D, M, N = v.shape
+    return max_cube_packed(pack_volume(v), N)
+
+
+def max_cube_packed(bits: np.ndarray, n: int) -> tuple[int, int, int, int]:
+    """As max_cube, from packed planes (D, M, ld_words) uint64."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    D, M, ldw = bits.shape
+    res = np.zeros(4, np.int64)
+    _check(lib().oracle_max_cube_packed(_ptr(bits), D, M, n, max(ldw, 1), _ptr(res)))
     return tuple(int(x) for x in res)

@@ -145,3 +145,38 @@ def rect_area_histogram_stack(a: np.ndarray) -> int:
                 best = max(best, heights[top] * (j - left))
             stack.append(j)
     return best
+
+
+# ---- largest all-ones cube of a volume (the higher-dimensional generalization of Section 6) ----
+
+def max_cube(v: np.ndarray) -> tuple[int, int, int, int]:
+    """Every cube checked through a 3-D prefix sum: (side, z, y, x) of its far corner (largest
+    z, y, x), the first in (z, y, x) order among the largest; (0, -1, -1, -1) when none."""
+    v = (np.asarray(v) != 0).astype(np.int64)
+    D, M, N = v.shape
+    P = np.zeros((D + 1, M + 1, N + 1), np.int64)
+    P[1:, 1:, 1:] = v.cumsum(0).cumsum(1).cumsum(2)
+
+    def ones(z, y, x, s):
+        z0, y0, x0 = z + 1 - s, y + 1 - s, x + 1 - s
+        return (P[z + 1, y + 1, x + 1] - P[z0, y + 1, x + 1] - P[z + 1, y0, x + 1]
+                - P[z + 1, y + 1, x0] + P[z0, y0, x + 1] + P[z0, y + 1, x0]
+                + P[z + 1, y0, x0] - P[z0, y0, x0])
+
+    best = (0, -1, -1, -1)
+    for s in range(1, min(D, M, N) + 1):
+        hit = None
+        for z in range(s - 1, D):
+            for y in range(s - 1, M):
+                for x in range(s - 1, N):
+                    if ones(z, y, x, s) == s ** 3:
+                        hit = (s, z, y, x)
+                        break
+                if hit:
+                    break
+            if hit:
+                break
+        if hit is None:
+            break
+        best = hit
+    return best

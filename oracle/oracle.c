@@ -22,7 +22,8 @@
  * (Section 3), with a record of where found_max_width is incremented.
  *
  * And the largest all-ones rectangle (the extension of Section 6's future work, in the
- * histogram form of Section 2.3), by its plain definition; see max_rect below.
+ * histogram form of Section 2.3), by its plain definition; see max_rect below.  And the largest
+ * all-ones cube of a binary volume (Section 6's higher dimensions); see oracle_max_cube_packed.
  *
  * Inputs: uint8 row-major (a cell is 1 iff its byte is non-zero), or packed uint64 rows where
  * column j is bit (j & 63) of word (j >> 6), padding bits ignored.
@@ -403,4 +404,69 @@ int oracle_max_rect_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t l
     if (rc) return rc;
     reader r = {NULL, bits, ld_words};
     return max_rect(&r, m, n, res);
+}
+
+/*
+ * ---- largest all-ones cube (the higher-dimensional generalization of Section 6) ----
+ * A binary volume A[z][y][x] of D planes of M rows of N columns.  The side map generalizes the
+ * recurrence of Section 2.1 eq. (1) from the three neighbours of a cell in the plane to the
+ * seven neighbours of a voxel that precede it along at least one axis:
+ *     c[z][y][x] = 0                                        if A[z][y][x] = 0
+ *     c[z][y][x] = 1 + min over (a, b, d) in {0,1}^3 \ {0} of c[z-a][y-b][x-d]   otherwise,
+ * with c = 0 outside the volume; c is the side of the largest all-ones cube whose far corner
+ * (largest z, y and x) is that voxel.  Reported: S = max c and the first far corner with c = S in
+ * (z, y, x) lexicographic order; (0, -1, -1, -1) when S = 0.  Two rolling planes of c.
+ * Input: packed planes, each M rows of ld_words words (column x = bit x & 63 of word x >> 6),
+ * plane z starting at word z * M * ld_words.
+ */
+int oracle_max_cube_packed(const uint64_t *bits, int64_t D, int64_t M, int64_t N,
+                           int64_t ld_words, int64_t res[4]) {
+    res[0] = 0;
+    res[1] = -1;
+    res[2] = -1;
+    res[3] = -1;
+    if (D < 0 || M < 0 || N < 0) return ORACLE_EINVAL;
+    if (D == 0 || M == 0 || N == 0) return ORACLE_OK;
+    if (!bits || ld_words < (N + 63) / 64) return ORACLE_EINVAL;
+    int32_t *prev = (int32_t *)calloc((size_t)(M * N), sizeof(int32_t));
+    int32_t *cur = (int32_t *)calloc((size_t)(M * N), sizeof(int32_t));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return ORACLE_ENOMEM;
+    }
+    for (int64_t z = 0; z < D; ++z) {
+        const uint64_t *plane = bits + z * M * ld_words;
+        for (int64_t y = 0; y < M; ++y) {
+            for (int64_t x = 0; x < N; ++x) {
+                int32_t v = 0;
+                if (cell_packed(plane, ld_words, y, x)) {
+                    int32_t m = INT32_MAX;
+                    for (int a = 0; a <= 1; ++a)
+                        for (int b = 0; b <= 1; ++b)
+                            for (int d = 0; d <= 1; ++d) {
+                                if (a == 0 && b == 0 && d == 0) continue;
+                                int32_t c = 0;
+                                if (z - a >= 0 && y - b >= 0 && x - d >= 0)
+                                    c = (a ? prev : cur)[(y - b) * N + (x - d)];
+                                if (c < m) m = c;
+                            }
+                    v = 1 + m;
+                }
+                cur[y * N + x] = v;
+                if (v > res[0]) {
+                    res[0] = v;
+                    res[1] = z;
+                    res[2] = y;
+                    res[3] = x;
+                }
+            }
+        }
+        int32_t *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    free(prev);
+    free(cur);
+    return ORACLE_OK;
 }
