@@ -183,6 +183,31 @@ typedef struct {
 ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                            int64_t ld_words, ms_rect *d_out, void *stream);
 
+/*
+ * Largest all-ones cube of a binary volume: the generalization to higher dimensions that the
+ * paper proposes as future work (Section 6).  The volume is D planes of M rows of N columns,
+ * packed like a matrix: row y of plane z is ld_words words starting at word
+ * (z * M + y) * ld_words (column x = bit x & 63 of word x >> 6).  The side map generalizes
+ * eq. (1) of Section 2.1 to seven neighbours: c = A ? 1 + min over the voxels that precede
+ * (z, y, x) by 0 or 1 along each axis (not all 0) : 0.
+ * Writes one ms_cube to d_out (device or pinned host memory): S = max c and the far corner
+ * (largest z, y, x) of a largest cube, the first in (z, y, x) order; {0, -1, -1, -1} when there
+ * is none.  d_workspace of ms_max_cube_workspace_size(D, M, N) bytes is caller-owned (three
+ * packed volumes and a control block).  This call BLOCKS: it synchronises `stream` after each
+ * probe of the side (about 2 log2 S times) to steer the search.
+ * Invalid: negative sizes, ld_words < ceil(N / 64), NULL bits (with cells), NULL d_out, NULL
+ * workspace (with cells), D * M * N >= 2^44.  MS_ERR_WORKSPACE_TOO_SMALL as usual;
+ * MS_ERR_UNSUPPORTED when D * M * ceil(N / 64) >= 2^32.
+ */
+typedef struct {
+    int64_t side, z, y, x;
+} ms_cube;
+ms_status ms_max_cube_workspace_size(ms_ctx *ctx, int64_t D, int64_t M, int64_t N,
+                                     size_t *bytes);
+ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M, int64_t N,
+                      int64_t ld_words, ms_cube *d_out, void *d_workspace,
+                      size_t workspace_bytes, void *stream);
+
 /* Autotuning.  ms_num_candidates / ms_candidate enumerate the launch shapes this build can
  * run; ms_set_config forces one (NULL restores tuned/default choices); ms_get_config reports
  * the shape that would be used for an m x n matrix.  ms_autotune times every candidate on the

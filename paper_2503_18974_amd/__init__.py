@@ -26,7 +26,8 @@ __all__ = [
     "ms_set_config", "ms_get_config", "ms_candidate", "ms_num_candidates", "ms_autotune",
     "ms_autotune_save", "ms_autotune_load", "Context", "pack_u8", "max_square", "square_map",
     "max_square_batched", "square_map_from_max", "area", "words_per_row",
-    "Rect", "ms_max_rectangle", "max_rectangle",
+    "Rect", "ms_max_rectangle", "max_rectangle", "Cube", "ms_max_cube",
+    "ms_max_cube_workspace_size", "max_cube",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +79,15 @@ class Rect:
     width: int
 
 
+@dataclass(frozen=True)
+class Cube:
+    """Largest all-ones cube of a volume: side and far corner (z, y, x)."""
+    side: int
+    z: int
+    y: int
+    x: int
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -113,6 +123,8 @@ def lib():
             "ms_all_max_squares": [_P, _P, _I64, _I64, _I64, _P, _P, _I64, _P, _P,
                                    ctypes.c_size_t, _P],
             "ms_max_rectangle": [_P, _P, _I64, _I64, _I64, _P, _P],
+            "ms_max_cube_workspace_size": [_P, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_size_t)],
+            "ms_max_cube": [_P, _P, _I64, _I64, _I64, _I64, _P, _P, ctypes.c_size_t, _P],
             "ms_autotune_save": [_P, ctypes.c_char_p],
             "ms_autotune_load": [_P, ctypes.c_char_p],
         }
@@ -354,6 +366,39 @@ def max_rectangle(bits, n: int, ctx=None, stream=None, out=None, sync: bool = Tr
     if not sync:
         return res
     return Rect(*(int(x) for x in res.cpu().tolist()))
+
+
+def ms_max_cube_workspace_size(ctx, D, M, N) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().ms_max_cube_workspace_size(ctx, D, M, N, ctypes.byref(n)),
+           "ms_max_cube_workspace_size")
+    return n.value
+
+
+def ms_max_cube(ctx, d_bits, D, M, N, ld_words, d_out, d_ws, ws_bytes, stream) -> int:
+    return lib().ms_max_cube(ctx, d_bits, D, M, N, ld_words, d_out, d_ws, ws_bytes, stream)
+
+
+def max_cube(bits, n: int, ctx=None, stream=None, workspace=None) -> Cube:
+    """Largest all-ones cube of a packed volume: an int64 CUDA tensor (D, M, >= ceil(n/64))
+    whose last dimension is contiguous and whose planes are contiguous rows.  Blocks until the
+    result is known (the search steers itself from the host)."""
+    torch = _torch()
+    if bits.dtype != torch.int64 or bits.dim() != 3 or not bits.is_cuda:
+        raise ValueError("packed volume must be a 3-D int64 CUDA tensor")
+    D, M, ldw = bits.shape
+    if D and M and n:
+        if bits.stride(2) != 1 or bits.stride(1) != ldw or bits.stride(0) != M * ldw:
+            raise ValueError("packed volume must be contiguous")
+        if ldw < words_per_row(n):
+            raise ValueError("packed rows are shorter than ceil(n/64) words")
+    need = ms_max_cube_workspace_size(_ctx(ctx), D, M, n)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=bits.device)
+    out = torch.empty(4, dtype=torch.int64, device=bits.device)
+    _check(ms_max_cube(_ctx(ctx), bits.data_ptr(), D, M, n, max(ldw, 1), out.data_ptr(),
+                       workspace.data_ptr(), workspace.numel(), _stream(stream)), "ms_max_cube")
+    return Cube(*(int(x) for x in out.cpu().tolist()))
 
 
 def all_max_squares(bits, n: int, result=None, capacity: int | None = None, ctx=None,

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmaxsq.so")
-SOURCES = ["kernels.hip", "rect.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "rect.hip", "cube.hip", "api.cpp"]
 ARCH = os.environ.get("MAXSQ_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

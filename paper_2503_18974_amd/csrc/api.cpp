@@ -73,6 +73,8 @@ struct ms_ctx {
     hipStream_t capture_stream = nullptr;
     // largest-rectangle scratch: header | one record per block of the launch
     void *rect_scratch = nullptr;
+    // pinned host words through which the cube search reads its device flags
+    uint64_t *pinned = nullptr;
     bool rect_dirty = false;
     std::mutex mu;
 };
@@ -269,7 +271,7 @@ ms_status ms_destroy(ms_ctx *ctx) {
         for (auto &kv : g_default)
             if (kv.second == ctx) return MS_ERR_INVALID_ARGUMENT;  // default contexts live on
     }
-    if (ctx->scratch || ctx->rect_scratch || !ctx->graphs.empty()) {
+    if (ctx->scratch || ctx->rect_scratch || ctx->pinned || !ctx->graphs.empty()) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
     }
@@ -277,6 +279,7 @@ ms_status ms_destroy(ms_ctx *ctx) {
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->rect_scratch) (void)hipFree(ctx->rect_scratch);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return MS_OK;
 }
@@ -474,6 +477,138 @@ ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64
                                            d_out);
     if (e != hipSuccess) c->rect_dirty = true;
     return hip_status(e);
+}
+
+namespace {
+
+ms_status validate_volume(const uint64_t *bits, int64_t D, int64_t M, int64_t N, int64_t ldw) {
+    if (D < 0 || M < 0 || N < 0 || ldw < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (D == 0 || M == 0 || N == 0) return MS_OK;
+    if (!bits || ldw < cdiv(N, 64)) return MS_ERR_INVALID_ARGUMENT;
+    if (mul_overflows(D, M) || mul_overflows(D * M, N) || D * M * N >= POS_LIMIT)
+        return MS_ERR_INVALID_ARGUMENT;
+    if (mul_overflows(D * M, ldw)) return MS_ERR_INVALID_ARGUMENT;
+    if (D * M * cdiv(N, 64) >= (int64_t(1) << 32)) return MS_ERR_UNSUPPORTED;
+    return MS_OK;
+}
+
+}  // namespace
+
+ms_status ms_max_cube_workspace_size(ms_ctx *ctx, int64_t D, int64_t M, int64_t N,
+                                     size_t *bytes) {
+    (void)ctx;
+    if (!bytes || D < 0 || M < 0 || N < 0) return MS_ERR_INVALID_ARGUMENT;
+    if (mul_overflows(D, M) || mul_overflows(D * M, std::max<int64_t>(cdiv(N, 64), 1)))
+        return MS_ERR_INVALID_ARGUMENT;
+    *bytes = mshost::cube_workspace_bytes(D, M, N);
+    return MS_OK;
+}
+
+ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M, int64_t N,
+                      int64_t ld_words, ms_cube *d_out, void *d_workspace,
+                      size_t workspace_bytes, void *stream) {
+    ms_status s = validate_volume(d_bits, D, M, N, ld_words);
+    if (s != MS_OK) return s;
+    if (!d_out) return MS_ERR_INVALID_ARGUMENT;
+    const bool empty = D == 0 || M == 0 || N == 0;
+    if (!empty && !d_workspace) return MS_ERR_INVALID_ARGUMENT;
+    if (!empty && workspace_bytes < mshost::cube_workspace_bytes(D, M, N))
+        return MS_ERR_WORKSPACE_TOO_SMALL;
+    ms_ctx *c = nullptr;
+    s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
+    if (!c->pinned) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) return MS_ERR_OUT_OF_MEMORY;
+        c->pinned = static_cast<uint64_t *>(p);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    ms_cube res{0, -1, -1, -1};
+    if (!empty) {
+        mshost::LaunchEnv env{c->num_cus, st};
+        auto *ctl = static_cast<mshost::CubeControl *>(d_workspace);
+        uint64_t *V[3];
+        for (int k = 0; k < 3; ++k) V[k] = mshost::cube_volume(d_workspace, D, M, N, k);
+        const uint64_t NONE = ~0ull;
+        // the first set voxel of the last x pass, read back through pinned memory
+        auto first_of = [&](uint64_t *f) -> ms_status {
+            if (hipMemcpyAsync(c->pinned, &ctl->first, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return MS_ERR_HIP;
+            *f = c->pinned[0];
+            return MS_OK;
+        };
+        const int64_t W = cdiv(N, 64);
+        // E_1: the input copied into volume 0 with its padding cleared
+        if (mshost::launch_cube_pass(env, 2, d_bits, ld_words, V[0], D, M, N, 0, ctl) !=
+            hipSuccess)
+            return MS_ERR_HIP;
+        uint64_t fa = NONE;
+        if ((s = first_of(&fa)) != MS_OK) return s;
+        if (fa != NONE) {
+            int cur = 0;
+            int64_t a = 1;
+            const int64_t smax = std::min(D, std::min(M, N));
+            // E_{a+b} from E_a (b <= a): one pass per axis; returns its first set voxel
+            auto step = [&](int64_t b, int *out, uint64_t *f) -> ms_status {
+                const int x = (cur + 1) % 3, y = (cur + 2) % 3;
+                if (mshost::launch_cube_pass(env, 0, V[cur], W, V[x], D, M, N, b, ctl) !=
+                        hipSuccess ||
+                    mshost::launch_cube_pass(env, 1, V[x], W, V[y], D, M, N, b, ctl) !=
+                        hipSuccess ||
+                    mshost::launch_cube_pass(env, 2, V[y], W, V[x], D, M, N, b, ctl) !=
+                        hipSuccess)
+                    return MS_ERR_HIP;
+                *out = x;
+                return first_of(f);
+            };
+            // gallop: a = 1, 2, 4, ... while E_{2a} is non-empty
+            int64_t failed = 0;
+            while (a < smax) {
+                const int64_t b = std::min(a, smax - a);
+                int out = 0;
+                uint64_t f = NONE;
+                if ((s = step(b, &out, &f)) != MS_OK) return s;
+                if (f == NONE) {
+                    failed = b;
+                    break;
+                }
+                cur = out;
+                a += b;
+                fa = f;
+            }
+            // the side is in [a, a + failed - 1]: add powers of two, largest first
+            const int64_t limit = a + failed - 1;
+            int64_t bstep = 1;
+            while (bstep * 2 <= failed - 1) bstep *= 2;
+            for (; failed > 1 && bstep >= 1; bstep /= 2) {
+                if (a + bstep > limit) continue;
+                int out = 0;
+                uint64_t f = NONE;
+                if ((s = step(bstep, &out, &f)) != MS_OK) return s;
+                if (f != NONE) {
+                    cur = out;
+                    a += bstep;
+                    fa = f;
+                }
+            }
+            const int64_t plane = M * N;
+            res.side = a;
+            res.z = (int64_t)(fa / (uint64_t)plane);
+            const int64_t rem = (int64_t)(fa % (uint64_t)plane);
+            res.y = rem / N;
+            res.x = rem % N;
+        }
+    }
+    // the result through pinned memory (d_out may be device or pinned host memory)
+    std::memcpy(c->pinned, &res, sizeof(res));
+    if (hipMemcpyAsync(d_out, c->pinned, sizeof(res), hipMemcpyDefault, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MS_ERR_HIP;
+    return MS_OK;
 }
 
 ms_status ms_all_max_squares_workspace_size(ms_ctx *ctx, int64_t m, int64_t n, size_t *bytes) {

@@ -108,4 +108,19 @@ int64_t rect_max_blocks(int num_cus);
 hipError_t launch_max_rect(const LaunchEnv &env, const uint64_t *bits, int64_t m, int64_t n,
                            int64_t ldw, RectScratch *rs, ms_rect *out);
 
+
+// Largest all-ones cube (cube.hip).  The workspace holds a 256-byte control block and three
+// volumes of D x M x ceil(n / 64) words; cube_volume(ws, .., k) is volume k (k < 3).
+struct CubeControl {
+    unsigned long long first;  // smallest z * M * n + y * n + x of a set voxel (~0: empty)
+    uint64_t pad[7];
+};
+size_t cube_workspace_bytes(int64_t D, int64_t M, int64_t n);
+uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k);
+// dst = src AND src shifted by d along `axis` (0 = z, 1 = y, 2 = x); the x pass also resets and
+// then sets ctl->first for dst.  src has row stride lds words; dst has ceil(n / 64).
+hipError_t launch_cube_pass(const LaunchEnv &env, int axis, const uint64_t *src, int64_t lds,
+                            uint64_t *dst, int64_t D, int64_t M, int64_t n, int64_t d,
+                            CubeControl *ctl);
+
 } // namespace mshost

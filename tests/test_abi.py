@@ -161,3 +161,23 @@ def test_max_rectangle_invalid(args):
 def test_max_rectangle_too_wide_is_unsupported():
     """Rows wider than 512 words are refused before any device work."""
     assert M.lib().ms_max_rectangle(None, P, 4, 32769, 513, P, None) == 5
+
+
+@pytest.mark.parametrize("args", [
+    (None, None, -1, 5, 5, 1, P, P, 1 << 20, None),        # negative D
+    (None, None, 2, 5, 5, 1, P, P, 1 << 20, None),         # null bits with voxels
+    (None, P, 2, 5, 130, 2, P, P, 1 << 20, None),          # ld_words < ceil(N/64)
+    (None, P, 2, 5, 5, 1, None, P, 1 << 20, None),         # null result
+    (None, P, 2, 5, 5, 1, P, None, 1 << 20, None),         # null workspace
+    (None, P, 1 << 15, 1 << 15, 1 << 15, 512, P, P, 1, None),  # D*M*N beyond 2^44
+])
+def test_max_cube_invalid(args):
+    assert M.lib().ms_max_cube(*args) == INVALID
+
+
+def test_max_cube_workspace_checked():
+    import ctypes as C
+    n = C.c_size_t()
+    assert M.lib().ms_max_cube_workspace_size(None, 3, 4, 130, C.byref(n)) == 0
+    assert n.value >= 3 * 3 * 4 * 3 * 8
+    assert M.lib().ms_max_cube(None, P, 3, 4, 130, 3, P, P, n.value - 1, None) == 2

@@ -24,6 +24,7 @@ __all__ = [
     "words_per_row", "pack_rows", "unpack_rows", "gen_bernoulli", "gen_bernoulli_packed",
     "gen_planted_packed", "gen_blob", "paper_grid", "paper_grid_seed", "c1", "batch_shapes",
     "gen_batch_matrix", "batch_packed", "large_packed", "LARGE", "serving_request", "CHUNK_ROWS",
+    "gen_bernoulli_volume", "gen_blob_volume", "pack_volume", "VOLUMES", "volume_packed",
 ]
 
 CHUNK_ROWS = 256
@@ -196,3 +197,55 @@ def serving_request(k: int, lo: int = 32, hi: int = 8192, seed: int = 30001):
     sub = int(rng.integers(0, 2**31 - 1))
     a8 = gen_blob(m, n, sigma, pct, sub)
     return pack_rows(a8), m, n, "blob", {"sigma": sigma, "percentile": pct}
+
+
+# ---- binary volumes (the higher-dimensional generalization the paper names as future work) ----
+
+def gen_bernoulli_volume(D: int, M: int, N: int, p: float, seed) -> np.ndarray:
+    """uint8 (D, M, N), voxels i.i.d. Bernoulli(p): ``default_rng(seed).random() < p`` drawn
+    plane by plane (equal to one full draw)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((D, M, N), np.uint8)
+    for z in range(D):
+        out[z] = rng.random((M, N)) < p
+    return out
+
+
+def gen_blob_volume(D: int, M: int, N: int, sigma: float, percentile: float, seed) -> np.ndarray:
+    """3-D 'blob' volume: standard-normal noise smoothed by a Gaussian of width sigma voxels
+    (reflect boundary, truncate at 4 sigma), thresholded above its given percentile."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((D, M, N), dtype=np.float32)
+    g = gaussian_filter(g, sigma, mode="reflect", truncate=4.0)
+    return (g > np.percentile(g, percentile)).astype(np.uint8)
+
+
+def pack_volume(v: np.ndarray, ld_words: int | None = None) -> np.ndarray:
+    """uint8/bool (D, M, N) -> uint64 (D, M, ld_words): every plane packed like a matrix."""
+    D, M, N = v.shape
+    ld = words_per_row(N) if ld_words is None else ld_words
+    out = np.zeros((D, M, max(ld, 1)), np.uint64)
+    for z in range(D):
+        if M and N:
+            out[z] = pack_rows(v[z], ld)
+    return out
+
+
+# Volumes for the cube benchmark: Bernoulli volumes at the densities where cubes of a few voxels
+# appear, and a blob volume whose cubes are tens of voxels wide.
+VOLUMES = {
+    "v256_p90": dict(D=256, M=256, N=256, kind="bernoulli", p=0.9, seed=41),
+    "v512_p95": dict(D=512, M=512, N=512, kind="bernoulli", p=0.95, seed=42),
+    "v256_blob": dict(D=256, M=256, N=256, kind="blob", sigma=4.0, pct=60.0, seed=43),
+}
+
+
+def volume_packed(name: str):
+    """(packed (D, M, W) uint64, D, M, N) of a named benchmark volume."""
+    c = VOLUMES[name]
+    if c["kind"] == "bernoulli":
+        v = gen_bernoulli_volume(c["D"], c["M"], c["N"], c["p"], c["seed"])
+    else:
+        v = gen_blob_volume(c["D"], c["M"], c["N"], c["sigma"], c["pct"], c["seed"])
+    return pack_volume(v), c["D"], c["M"], c["N"]
