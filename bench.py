@@ -15,8 +15,9 @@ map launch inside the timed steps) against the 8 TB/s HBM peak; the batched entr
 the same 45 packed matrices next to the per-matrix loop; the three large single matrices
 (32768^2 p=0.9, 4096 x 262144 with a planted 1500^2 block, 16384^2 blob) with the caches
 flushed before every timed call; the 10000-matrix batched workload against the plain
-per-matrix loop; the largest all-ones rectangle on the grid and the large matrices; and the
-CPU oracle (plus the paper's Algorithm 1 in C) timed on the host.
+per-matrix loop; the largest all-ones rectangle on the grid and the large matrices; the largest
+all-ones cube of three volumes; and the CPU oracle (plus the paper's Algorithm 1 in C) timed on
+the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-large] [--no-c4]
 """
@@ -306,6 +307,51 @@ def rect_section(L, h, dev, B, mats, golden_all, reps, large_names):
     return res
 
 
+def cube_section(L, h, dev, golden_all, reps):
+    """Largest all-ones cube (ms_max_cube) of the benchmark volumes, checked against the
+    oracle's stored values, then timed: the call blocks (its search reads a flag per probe), so
+    the wall clock around it is the figure."""
+    import ctypes
+    import hashlib
+    import numpy as np
+    import torch
+    import workloads as W
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    out = {}
+    for name in sorted(W.VOLUMES):
+        g = golden_all["volumes"][name]
+        bits, D, M, N = W.volume_packed(name)
+        if hashlib.sha256(bits.tobytes()).hexdigest() != g["sha256_packed"]:
+            raise SystemExit("%s: regenerated volume differs from the recorded one" % name)
+        d = torch.from_numpy(bits.view(np.int64)).to(dev)
+        del bits
+        nb = ctypes.c_size_t()
+        L.ms_max_cube_workspace_size(h, D, M, N, ctypes.byref(nb))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        o = torch.zeros(4, dtype=torch.int64, device=dev)
+        if L.ms_max_cube(h, d.data_ptr(), D, M, N, d.size(2), o.data_ptr(), ws.data_ptr(),
+                         nb.value, sp):
+            raise RuntimeError("ms_max_cube failed")
+        got = o.cpu().tolist()
+        if got != [g["side"], g["z"], g["y"], g["x"]]:
+            raise SystemExit("cube %s: %s vs oracle %s" % (name, got, g))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            L.ms_max_cube(h, d.data_ptr(), D, M, N, d.size(2), o.data_ptr(), ws.data_ptr(),
+                          nb.value, sp)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        vox = D * M * N
+        out[name] = {"D": D, "M": M, "N": N, "side": g["side"], "ms_per_call": t * 1e3,
+                     "gvoxels_s": vox / t / 1e9}
+        log("cube %s %dx%dx%d side %d: %.3f ms per call (%.0f Gvoxels/s)"
+            % (name, D, M, N, g["side"], t * 1e3, vox / t / 1e9))
+        del d, ws
+    return out
+
+
 def hbm_achievable(dev, reps=5):
     """Bandwidth plain streaming kernels reach on this device: read-mostly (an elementwise
     compare of two 512 MiB halves), write-only (a 1 GiB fill) and copy (512 MiB each way), best
@@ -501,6 +547,7 @@ def main():
                     help="streams for the multi-stream grid step (1 skips it)")
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-rect", action="store_true")
+    ap.add_argument("--no-cube", action="store_true")
     ap.add_argument("--c4-reps", type=int, default=10)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -724,6 +771,8 @@ def main():
         log("batched %.3f ms vs per-matrix loop %.3f ms" % (t_b, t_p))
 
     extra["hbm_achievable"] = hbm_achievable(dev)
+    if not args.no_cube:
+        extra["cube"] = cube_section(L, h, dev, golden_all, 5)
     if not args.no_rect:
         extra["rect"] = rect_section(L, h, dev, B, mats, golden_all, 5,
                                      [] if args.no_large else ["c3a", "c3c"])

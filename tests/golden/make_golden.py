@@ -7,6 +7,8 @@ same bits.  Calls only the oracle and the input generators.
 
 --rect adds, to the existing records, the oracle's largest all-ones rectangle as
 "rect": [area, row, col, height, width] (rows of at most 32768 columns only).
+--cube writes "volumes": the oracle's largest all-ones cube (side, z, y, x) of every benchmark
+volume, with a sha256 of the packed volume.
 
 The batched workload's 10000 results go to c4_results.txt instead (one line per matrix).
 """
@@ -92,9 +94,23 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", default="c1,c2,c3a,c3b,c3c")
     ap.add_argument("--rect", action="store_true")
+    ap.add_argument("--cube", action="store_true")
     args = ap.parse_args()
     want = set(args.only.split(","))
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    if args.cube:
+        vols = {}
+        for name in sorted(W.VOLUMES):
+            t = time.time()
+            bits, D, M, N = W.volume_packed(name)
+            s_, z, y, x = oracle.max_cube_packed(bits, N)
+            vols[name] = {"D": D, "M": M, "N": N, "side": s_, "z": z, "y": y, "x": x,
+                          "sha256_packed": sha(bits)}
+            print(name, vols[name], "%.1fs" % (time.time() - t), flush=True)
+        data["volumes"] = vols
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        return
     if args.rect:
         add_rects(data, want)
         with open(OUT, "w") as f:

@@ -112,3 +112,20 @@ def test_repeated_calls(dev):
             check(v, dev, ctx=ctx)
     finally:
         ctx.close()
+
+
+def test_benchmark_volumes(dev):
+    """The benchmark's volumes (up to 512^3) against the oracle's stored results."""
+    import hashlib
+    import json
+    import os
+    import torch
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                         "oracle_configs.json")))["volumes"]
+    for name in sorted(W.VOLUMES):
+        announce("cube volume", name)
+        bits, D, Mr, N = W.volume_packed(name)
+        g = golden[name]
+        assert hashlib.sha256(bits.tobytes()).hexdigest() == g["sha256_packed"]
+        c = M.max_cube(torch.from_numpy(bits.view(np.int64)).to(dev), N)
+        assert (c.side, c.z, c.y, c.x) == (g["side"], g["z"], g["y"], g["x"])
