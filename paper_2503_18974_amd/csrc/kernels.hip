@@ -346,40 +346,84 @@ __global__ __launch_bounds__(256) void k_dpmap_wide(const uint64_t *__restrict__
     R = R < m ? R : m;
     const int64_t items = ((m + R - 1) / R) * nwin;
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    for (int64_t it = blockIdx.x; it < items; it += nblk) {
-        const int64_t bnd_i = it / nwin, wdx = it - bnd_i * nwin;
-        const int64_t ra = bnd_i * R, rb = ra + R < m ? ra + R : m;
-        const int64_t rh = ra - S > 0 ? ra - S : 0;
-        const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
-        const int64_t xh = xa - hc > 0 ? xa - hc : 0;
-        const int ngi = (int)((xb - xh + GW - 1) / GW);
-        if (region) {
+    if (!region) {
+        for (int64_t it = blockIdx.x; it < items; it += nblk) {
+            const int64_t bnd_i = it / nwin, wdx = it - bnd_i * nwin;
+            const int64_t ra = bnd_i * R, rb = ra + R < m ? ra + R : m;
+            const int64_t rh = ra - S > 0 ? ra - S : 0;
+            const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
+            const int64_t xh = xa - hc > 0 ? xa - hc : 0;
+            const int ngi = (int)((xb - xh + GW - 1) / GW);
+            dprun_block<false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp, vec_ok != 0,
+                               L, StoreClass<2>{});
+        }
+        return;
+    }
+    // Region mode: only items touching a tile bounded above REGION_SMALL (or saturated) have
+    // cells to store, and they cluster around the large squares, so dealing items to blocks by
+    // index would stack several on one block.  Every block instead ranks those items in item
+    // order (a pass over all items, 256 per round: a ballot per wave and the four wave counts)
+    // and maps the ones whose rank is its index modulo the grid.
+    __shared__ int32_t s_cnt[4];
+    __shared__ int32_t s_nsel;
+    __shared__ int64_t s_sel[256];
+    int64_t before = 0;  // active items in earlier rounds (the same in every thread)
+    for (int64_t c0 = 0; c0 < items; c0 += 256) {
+        const int64_t it = c0 + threadIdx.x;
+        bool act = false;
+        if (it < items) {
+            const int64_t bnd_i = it / nwin, wdx = it - bnd_i * nwin;
+            const int64_t ra = bnd_i * R, rb = ra + R < m ? ra + R : m;
+            const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
+            for (int64_t ty = ra / tile_rows; ty <= (rb - 1) / tile_rows; ++ty)
+                for (int64_t tc = xa / TILE_COLS; tc <= (xb - 1) / TILE_COLS; ++tc) {
+                    const int32_t bv = bounds[ty * tile_ntx + tc];
+                    act |= bv < 0 || bv > REGION_SMALL;
+                }
+        }
+        const uint64_t bal = __ballot(act);
+        if (lane == 0) s_cnt[wv] = __popcll(bal);
+        if (threadIdx.x == 0) s_nsel = 0;
+        __syncthreads();
+        int32_t wbase = 0;
+        for (int w = 0; w < wv; ++w) wbase += s_cnt[w];
+        const int64_t ctotal = (int64_t)s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        if (act) {
+            const int64_t rank = before + wbase + __popcll(bal & ((1ull << lane) - 1));
+            if (rank % nblk == blockIdx.x) s_sel[atomicAdd(&s_nsel, 1)] = it;
+        }
+        __syncthreads();
+        const int nsel = s_nsel;
+        for (int k = 0; k < nsel; ++k) {
+            const int64_t it2 = s_sel[k];
+            const int64_t bnd_i = it2 / nwin, wdx = it2 - bnd_i * nwin;
+            const int64_t ra = bnd_i * R, rb = ra + R < m ? ra + R : m;
+            const int64_t rh = ra - S > 0 ? ra - S : 0;
+            const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
+            const int64_t xh = xa - hc > 0 ? xa - hc : 0;
+            const int ngi = (int)((xb - xh + GW - 1) / GW);
             StoreClass<2> sc;
             sc.on = true;
             sc.tile_rows = tile_rows;
             sc.ty0 = ra / tile_rows;
             const int64_t nk = (rb - 1) / tile_rows - sc.ty0 + 1;  // 2 or 3
-            bool any = false;
 #pragma unroll
             for (int gl = 0; gl < 2; ++gl) {
                 sc.cls[gl] = 0;
                 const int64_t col = xh + (int64_t)(wv * 2 + gl) * GW + (int64_t)lane * 4;
                 if (wv * 2 + gl < ngi && col >= xa && col < xb) {
                     const int64_t tc = col / TILE_COLS;
-                    for (int64_t k = 0; k < nk; ++k) {
-                        const int32_t bv = bounds[(sc.ty0 + k) * tile_ntx + tc];
-                        if (bv < 0 || bv > REGION_SMALL) sc.cls[gl] |= 1ull << k;
+                    for (int64_t kk = 0; kk < nk; ++kk) {
+                        const int32_t bv = bounds[(sc.ty0 + kk) * tile_ntx + tc];
+                        if (bv < 0 || bv > REGION_SMALL) sc.cls[gl] |= 1ull << kk;
                     }
                 }
-                any |= sc.cls[gl] != 0;
             }
-            if (!__syncthreads_or(any)) continue;   // block-uniform
             dprun_block<true>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp, vec_ok != 0,
                               L, sc);
-        } else {
-            dprun_block<false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp, vec_ok != 0,
-                               L, StoreClass<2>{});
         }
+        before += ctotal;
+        __syncthreads();  // the next round rewrites s_cnt, s_nsel and s_sel
     }
 }
 
