@@ -703,17 +703,17 @@ __device__ __forceinline__ int64_t sat_run(const uint8_t *__restrict__ sat, int6
     }
 }
 
-// One pass over the tile with heights clamped at depth U and a window of U columns to the left
-// of the tile: *best / *bpos receive the tile's largest computed side and its first cell.  A
+// One pass over rows [ra, rb) of a tile with heights clamped at depth U and a window of U columns
+// to the left of the tile: *best / *bpos receive the rows' largest computed side and its first
+// cell.  A
 // true side s >= U still computes as >= U (clamping and clipping cannot push a value below U),
 // so a result below U is exact.  Returns false if the window exceeds one word per lane.
 template <class TS>
 __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
-                             int64_t ldw, int64_t ty, int64_t tx, int64_t U, int32_t *best_out,
-                             int64_t *bpos_out) {
+                             int64_t ldw, int64_t ra, int64_t rb, int64_t tx, int64_t U,
+                             int32_t *best_out, int64_t *bpos_out) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
-    const int64_t ra = ty * TS::TR, rb = ra + TS::TR < m ? ra + TS::TR : m;
     const int64_t xa = tx * OWN_COLS, xb = xa + OWN_COLS < n ? xa + OWN_COLS : n;
     const int64_t nwords = (n + 63) >> 6;
     const int64_t w0 = xa - U > 0 ? ((xa - U) >> 6) : 0;
@@ -800,16 +800,20 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
     return true;
 }
 
-// Records the tile's bound when the caller keeps bounds.
+// Records the tile's bound when the caller keeps bounds: the largest over the parts of the tile
+// (the probe left -1 there).
 __device__ __forceinline__ void note_bound(int32_t *bounds, int64_t t, int64_t bound) {
-    if (bounds && __lane_id() == 0) bounds[t] = (int32_t)bound;
+    if (bounds && __lane_id() == 0) atomicMax(&bounds[t], (int32_t)bound);
 }
 
+// Finishes rows [ra + part * ceil(TR / nparts), ...) of a saturated tile: the tile's rows split
+// into nparts parts handled by different waves, each exact for its rows.
 template <class TS>
 __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
                              int64_t ldw, int64_t ty, int64_t tx, int64_t ntx,
                              const uint8_t *__restrict__ sat, unsigned long long *key,
-                             uint32_t *serial_flag, int32_t *bounds = nullptr) {
+                             uint32_t *serial_flag, int32_t *bounds = nullptr, int part = 0,
+                             int nparts = 1) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
     m = uniform(m);
@@ -817,6 +821,11 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
     ldw = uniform(ldw);
     ty = uniform(ty);
     tx = uniform(tx);
+    const int64_t prow = (TS::TR + nparts - 1) / nparts;
+    const int64_t ta = ty * TS::TR, tb = ta + TS::TR < m ? ta + TS::TR : m;
+    const int64_t ra = ta + part * prow < tb ? ta + part * prow : tb;
+    const int64_t rb = ra + prow < tb ? ra + prow : tb;
+    if (ra >= rb) return;
     const int64_t vrun = uniform(sat_run(sat, ty * ntx + tx, ntx, ty + 1, lane));
     const int64_t hrun = uniform(sat_run(sat, ty * ntx + tx, 1, tx + 1, lane));
     int64_t ucap = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
@@ -837,7 +846,7 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
         U = U < ucap ? U : ucap;
         int32_t best = 0;
         int64_t bpos = 0;
-        if (!resolve_pass<TS>(bits, m, n, ldw, ty, tx, U, &best, &bpos)) {
+        if (!resolve_pass<TS>(bits, m, n, ldw, ra, rb, tx, U, &best, &bpos)) {
             if (lane == 0) atomicOr(serial_flag, 1u);  // the serial pass finishes the matrix
             return;
         }

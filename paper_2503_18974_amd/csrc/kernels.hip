@@ -155,6 +155,9 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
 // the waves so that clustered saturated tiles land on different waves; the last wave to finish
 // (a completion count, no waiting) writes the result.  With no saturated tile, the first wave
 // writes it at once and every other wave returns.
+// Waves sharing one saturated tile in k_resolve (a divisor of the 4 waves of a block).
+constexpr int RESOLVE_PARTS = 4;
+
 template <class TS>
 __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bits, int64_t m,
                                                  int64_t n, int64_t ldw, int64_t ntiles,
@@ -170,17 +173,24 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
         if (wave == 0) finalize_wave(bits, m, n, ldw, hdr, serial_state, out);
         return;
     }
-    // tiles wave, wave + nwave, ...: 64 saturation bytes per round
-    for (int64_t base = wave; base < ntiles; base += 64 * nwave) {
-        const int64_t t = base + (int64_t)lane * nwave;
+    // With few saturated tiles (a wide square: each one's height scan is long and there are
+    // waves to spare) RESOLVE_PARTS waves share each tile, part = wave % parts taking a slice of
+    // its rows; with many (blob images) one wave takes a whole tile, since every part repeats
+    // the scan of the rows above.  Groups of `parts` waves take tiles g, g + ngroups, ...: 64
+    // saturation bytes per round.
+    const int parts = (int64_t)nsat * RESOLVE_PARTS <= nwave ? RESOLVE_PARTS : 1;
+    const int64_t grp = wave / parts, ngrp = nwave / parts;
+    const int part = (int)(wave % parts);
+    for (int64_t base = grp; base < ntiles; base += 64 * ngrp) {
+        const int64_t t = base + (int64_t)lane * ngrp;
         uint64_t b = __ballot(t < ntiles && sat[t] != 0);
         while (b) {
             const int l = __ffsll((long long)b) - 1;
             b &= b - 1;
-            const int64_t tt = base + (int64_t)l * nwave;
+            const int64_t tt = base + (int64_t)l * ngrp;
             const int64_t ty = tt / ntx, tx = tt - ty * ntx;
             resolve_tile<TS>(bits, m, n, ldw, ty, tx, ntx, sat, &hdr->key, &hdr->serial_flag,
-                             bounds);
+                             bounds, part, parts);
         }
     }
     __threadfence();
