@@ -498,12 +498,40 @@ def c4_section(L, h, dev, reps):
     t_l = e0.elapsed_time(e1) / loop_reps * 1e-3
     log("c4: batched %.3f ms (%.0f Gcells/s) vs plain loop %.1f ms (%.0f Gcells/s)"
         % (t_b * 1e3, cells / t_b / 1e9, t_l * 1e3, cells / t_l / 1e9))
+    # the batched autotuner on this batch (its own context), then the same launches captured
+    # once into a HIP graph and replayed
+    ctx_t = M.Context()
+    bt = M.Batch(items, ctx=ctx_t)
+    bt.autotune(stream)
+    extra = {}
+    for mode in ("tuned", "tuned_graph"):
+        if mode == "tuned_graph":
+            os.environ["MAXSQ_GRAPH"] = "1"
+        bt.out.fill_(-9)
+        bt.run(stream)
+        torch.cuda.synchronize()
+        if not np.array_equal(np.array(bt.out[:count].cpu().tolist()), ref[:, 3:6]):
+            raise SystemExit("c4: %s batched results differ from the oracle" % mode)
+        e0.record(stream)
+        for _ in range(reps):
+            bt.run(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tm = e0.elapsed_time(e1) / reps * 1e-3
+        extra["batched_%s_ms" % mode] = tm * 1e3
+        extra["batched_%s_gcells_s" % mode] = cells / tm / 1e9
+        log("c4: batched, %s: %.3f ms (%.0f Gcells/s)" % (mode.replace("_", ", "), tm * 1e3,
+                                                         cells / tm / 1e9))
+    os.environ.pop("MAXSQ_GRAPH", None)
+    del bt
+    ctx_t.close()
     out = {"matrices": count, "cells": cells, "packed_bytes": int(offs[-1]) * 8,
            "batched_ms": t_b * 1e3, "batched_gcells_s": cells / t_b / 1e9,
            "batched_gbs": cells * PROBE_BYTES_PER_CELL / t_b / 1e9,
            "plain_loop_ms": t_l * 1e3, "plain_loop_gcells_s": cells / t_l / 1e9,
            "plain_loop_wall_ms": t_wall * 1e3,
            "speedup": t_l / t_b}
+    out.update(extra)
     del batch, big, items, res
     torch.cuda.empty_cache()
     return out

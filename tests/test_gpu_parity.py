@@ -248,3 +248,13 @@ def test_map_regions_mixed(dev, spots):
         c0 = 1700 * k + int(rng.integers(0, 1700 - s))
         a[r0:r0 + s, c0:c0 + s] = 1
     assert_same(a, dev)
+
+
+def test_wide_map_unaligned_rows(dev):
+    """A square beyond the narrow reach with a map row stride that is not a multiple of four:
+    the block-wide kernel's scalar stores, in both halo classes."""
+    announce("wide map unaligned")
+    rng = np.random.default_rng(77)
+    a = (rng.random((1000, 1500)) < 0.75).astype(np.uint8)
+    a[200:800, 300:900] = 1
+    assert_same(a, dev, dp_extra=3)
