@@ -868,7 +868,7 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
 // double-buffered LDS slot written after each row, with one barrier per row.  Every loop trip
 // count here is uniform over the block, so all waves meet every barrier.
 // ----------------------------------------------------------------------------------------------
-constexpr int BLK_WORDS = 4096;  // staged packed words per block
+constexpr int BLK_WORDS = 2048;  // staged packed words per block (24 KB with the row runs)
 
 struct BlockLds {
     uint64_t *x;     // BLK_WORDS packed words

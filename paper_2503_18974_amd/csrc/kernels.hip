@@ -203,51 +203,21 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
     }
 }
 
-// ---------------------------------------------------------------------------------- map
-// One instantiation per window width: a kernel acts only when s_lo < S <= its window's reach
-// (and, when `serial_beyond`, runs the serial sweep for any larger S), so a narrow, lean kernel
-// serves the common small squares and a wide one the rest; the other exits at once.
-// Band height: at least band_rows and 4 S (so the S-row head start costs at most a quarter),
-// halved while that leaves fewer items than waves, down to 2 S (or 16 rows).
-// Region mode (bounds != nullptr, only for a search that ran in the same call): each probe tile
-// carries an upper bound on its largest side.  When S exceeds the narrow reach, the narrow kernel
-// uses REGION_SMALL halos and stores only cells of tiles bounded by REGION_SMALL; the wide kernel
-// uses S, skips items touching no other tile, and stores only cells of the other tiles.  A cell
-// is exact whenever the halo is at least its own dp.
+// The narrow pass of the map (one wave per item, windows of NGMAX groups of 64 * CPL columns):
+// every cell when S <= MAP_NARROW_REACH; in region mode (S beyond the reach, per-tile bounds of
+// a search in the same call) the cells of the tiles bounded by REGION_SMALL, with REGION_SMALL
+// halos.  Band height: at least band_rows and 4 S (so the S-row head start costs at most a
+// quarter), halved while that leaves fewer items than min_items, down to 2 S (or 16 rows).
 template <int NGMAX, int CPL>
-__global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits, int64_t m,
-                                               int64_t n, int64_t ldw, int32_t *__restrict__ dp,
-                                               int64_t ld_dp,
-                                               const ms_square *__restrict__ maxsq,
-                                               int64_t band_rows, int32_t *serial_state,
-                                               int vec_ok, int64_t s_lo, int serial_beyond,
-                                               const int32_t *__restrict__ bounds,
-                                               int64_t tile_rows, int64_t tile_ntx,
-                                               int64_t min_items) {
+__device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                            int32_t *__restrict__ dp, int64_t ld_dp, int64_t S,
+                            int64_t band_rows, int vec_ok, bool region,
+                            const int32_t *__restrict__ bounds, int64_t tile_rows,
+                            int64_t tile_ntx, int64_t min_items, WaveLds lds) {
     constexpr int64_t GW = 64 * CPL;
-    constexpr int64_t WIN = NGMAX * GW;
-    constexpr int64_t REACH = WIN - 64;   // largest S whose halo leaves a 64-column output
-    constexpr int LDSW = NGMAX * CPL <= 8 ? LDS_WORDS / 2 : LDS_WORDS;
     constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
-    __shared__ uint64_t lx[4][LDSW];
-    __shared__ int32_t lc[4][LDSW];
-    const WaveLds lds{lx[threadIdx.x / WAVE], lc[threadIdx.x / WAVE], LDSW};
-    const int64_t S = uniform(maxsq->side);
-    if (S <= s_lo) return;
-    const bool region = bounds != nullptr && S > MAP_NARROW_REACH;
-    const bool wide_pass = s_lo >= 0;           // this launch owns the tiles beyond the reach
-    int64_t Sg = S;                             // the side the halos must cover
-    if (region && !wide_pass) Sg = REGION_SMALL;
+    const int64_t Sg = region ? REGION_SMALL : S;  // the side the halos must cover
     const int64_t hc = (Sg + 63) & ~(int64_t)63;
-    if (hc > REACH) {
-        // too large for this window: one wave sweeps the whole matrix (widest kernel only)
-        if (serial_beyond && blockIdx.x == 0 && threadIdx.x < WAVE) {
-            const int64_t nw64 = ((n + 63) >> 6) * 64;
-            Track tr{0, INT64_MAX};
-            serial_dp<true>(bits, m, n, ldw, dp, ld_dp, serial_state, serial_state + nw64, tr);
-        }
-        return;
-    }
     int64_t ng = (hc + (4 * hc > 256 ? 4 * hc : 256) + GW - 1) / GW;
     ng = ng < 1 ? 1 : (ng > NGMAX ? NGMAX : ng);
     const int64_t rmin = 2 * Sg > 16 ? 2 * Sg : 16;
@@ -264,12 +234,8 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
     // the tallest bands (the least halo work) that still leave min_items items
     int64_t R = band_rows > 4 * Sg ? band_rows : 4 * Sg;
     while (R > rmin && ((m + R - 1) / R) * nwin < min_items) R = (R / 2 > rmin) ? R / 2 : rmin;
-    if (region) {
-        // the wide pass touches few items: short bands spread them over more waves; either pass
-        // keeps an item within 32 tile rows (one mask bit per tile row)
-        if (wide_pass) R = 2 * tile_rows;
-        R = R < 32 * tile_rows ? R : 32 * tile_rows;
-    }
+    // in region mode an item stays within 32 tile rows (one mask bit per tile row)
+    if (region) R = R < 32 * tile_rows ? R : 32 * tile_rows;
     R = R < m ? R : m;
     const int64_t items = ((m + R - 1) / R) * nwin;
     const int lane = __lane_id();
@@ -297,12 +263,12 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
                     for (int64_t k = 0; k < nk; ++k) {
                         const int32_t bnd = bounds[(sc.ty0 + k) * tile_ntx + tc];
                         const bool big = bnd < 0 || bnd > REGION_SMALL;
-                        if (big == wide_pass) sc.cls[g] |= 1ull << k;
+                        if (!big) sc.cls[g] |= 1ull << k;
                     }
                 }
                 any |= sc.cls[g] != 0;
             }
-            if (!__ballot(any)) continue;  // nothing of this pass's class here
+            if (!__ballot(any)) continue;  // no small tile here
             dprun<NGMAX, CPL, true, false, true>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp,
                                                  ld_dp, vec_ok != 0, dummy, lds, sc);
         } else {
@@ -312,26 +278,17 @@ __global__ __launch_bounds__(256) void k_dpmap(const uint64_t *__restrict__ bits
     }
 }
 
-// Wide dp map (448 < S <= 1984): windows of 2048 columns, one window per block (dprun_block),
-// items distributed per block so that the block's barriers stay uniform.  Region mode as in
-// k_dpmap: items touching no tile bounded above REGION_SMALL are skipped, and only cells of such
-// tiles are stored.  Beyond 1984 one wave sweeps the whole matrix.
-__global__ __launch_bounds__(256) void k_dpmap_wide(const uint64_t *__restrict__ bits, int64_t m,
-                                                    int64_t n, int64_t ldw,
-                                                    int32_t *__restrict__ dp, int64_t ld_dp,
-                                                    const ms_square *__restrict__ maxsq,
-                                                    int64_t band_rows, int32_t *serial_state,
-                                                    int vec_ok,
-                                                    const int32_t *__restrict__ bounds,
-                                                    int64_t tile_rows, int64_t tile_ntx) {
+// The wide pass of the map (MAP_NARROW_REACH < S <= 1984): windows of 2048 columns, one window
+// per block (dprun_block), items distributed per block so that the block's barriers stay
+// uniform.  In region mode only the cells of tiles bounded above REGION_SMALL (or saturated) are
+// stored, with S halos.  Beyond 1984 one wave sweeps the whole matrix.
+__device__ void wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                          int32_t *__restrict__ dp, int64_t ld_dp, int64_t S, int64_t band_rows,
+                          int32_t *serial_state, int vec_ok, bool region,
+                          const int32_t *__restrict__ bounds, int64_t tile_rows,
+                          int64_t tile_ntx, BlockLds L) {
     constexpr int64_t GW = 256, NGB = 8, WIN = NGB * GW, REACH = WIN - 64;
     constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
-    __shared__ uint64_t lx[BLK_WORDS];
-    __shared__ int32_t lc[BLK_WORDS];
-    __shared__ int32_t lslot[8];
-    const BlockLds L{lx, lc, lslot};
-    const int64_t S = uniform(maxsq->side);
-    if (S <= MAP_NARROW_REACH) return;
     const int64_t hc = (S + 63) & ~(int64_t)63;
     if (hc > REACH) {
         if (blockIdx.x == 0 && threadIdx.x < WAVE) {
@@ -341,7 +298,6 @@ __global__ __launch_bounds__(256) void k_dpmap_wide(const uint64_t *__restrict__
         }
         return;
     }
-    const bool region = bounds != nullptr;
     const int64_t ow = WIN - hc;
     const int64_t nwin = (n + ow - 1) / ow;
     const int64_t nblk = gridDim.x;
@@ -434,6 +390,43 @@ __global__ __launch_bounds__(256) void k_dpmap_wide(const uint64_t *__restrict__
         }
         before += ctotal;
         __syncthreads();  // the next round rewrites s_cnt, s_nsel and s_sel
+    }
+}
+
+// ---------------------------------------------------------------------------------- map
+// One launch per map: a narrow pass (one wave per item, 512-column windows) for S up to
+// MAP_NARROW_REACH, a wide pass (one block per item, 2048-column windows) beyond it, and in region
+// mode (bounds != nullptr: each probe tile of a search in the same call carries an upper bound on
+// its largest side) both, split by tile: the narrow pass maps the tiles bounded by REGION_SMALL
+// with REGION_SMALL halos, the wide pass the others with S halos.  A cell is exact whenever its
+// halo is at least its own dp.  Both passes share the block's 24 KB of LDS (the narrow pass as
+// four per-wave regions); registers are held to five waves per SIMD without spilling.
+template <int NGMAX, int CPL>
+__global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ bits, int64_t m,
+                                               int64_t n, int64_t ldw, int32_t *__restrict__ dp,
+                                               int64_t ld_dp,
+                                               const ms_square *__restrict__ maxsq,
+                                               int64_t band_rows, int32_t *serial_state,
+                                               int vec_ok, const int32_t *__restrict__ bounds,
+                                               int64_t tile_rows, int64_t tile_ntx,
+                                               int64_t min_items) {
+    constexpr int LDSW = BLK_WORDS / 4;  // words per wave in the narrow pass
+    static_assert(NGMAX * CPL * 64 <= LDSW, "a row chunk holds at least 64 rows");
+    __shared__ uint64_t lx[BLK_WORDS];
+    __shared__ int32_t lc[BLK_WORDS];
+    __shared__ int32_t lslot[8];
+    const int64_t S = uniform(maxsq->side);
+    const bool region = bounds != nullptr && S > MAP_NARROW_REACH;
+    if (S <= MAP_NARROW_REACH || region) {
+        const int wv = threadIdx.x / WAVE;
+        narrow_pass<NGMAX, CPL>(bits, m, n, ldw, dp, ld_dp, S, band_rows, vec_ok, region, bounds,
+                                tile_rows, tile_ntx, min_items,
+                                WaveLds{lx + wv * LDSW, lc + wv * LDSW, LDSW});
+    }
+    if (S > MAP_NARROW_REACH) {
+        __syncthreads();  // the wide pass takes the block's LDS as one region
+        wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state, vec_ok, region, bounds,
+                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot});
     }
 }
 
@@ -862,29 +855,18 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
     const int64_t trows = regions ? regions->tile_rows : 1;
     const int64_t tntx = regions ? regions->tile_ntx : 1;
     const int64_t min_items = (int64_t)env.num_cus * 4 * MAP_ITEMS_PER_SIMD;
-    // narrow kernel: squares up to 448 (8 x 64 - 64); window 512 columns, 1 or 2 groups
-    constexpr int64_t NARROW_REACH = msk::MAP_NARROW_REACH;
+    // one kernel: the narrow pass (512-column windows as 2 x 4 or 1 x 8 columns per lane) and,
+    // for squares beyond its reach, the block-wide pass
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
-                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0,
-                           bounds, trows, tntx, min_items);
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
+                           min_items);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
-                           maxsq, (int64_t)band_rows, serial_state, vec_ok, (int64_t)-1, 0,
-                           bounds, trows, tntx, min_items);
+                           maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
+                           min_items);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // a square wider than the narrow kernel's reach can only exist when both sides exceed it
-    if (std::min(m, n) > NARROW_REACH) {
-        // three 48 KB blocks fit a CU
-        const dim3 gw((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks,
-                                                                        (int64_t)env.num_cus * 3)));
-        hipLaunchKernelGGL(msk::k_dpmap_wide, gw, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
-                           maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx);
-        e = hipGetLastError();
-    }
-    return e;
+    return hipGetLastError();
 }
 
 hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,
