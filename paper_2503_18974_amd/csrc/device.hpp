@@ -116,6 +116,21 @@ __device__ __forceinline__ Track wave_track(Track t) {
     return Track{best, p};
 }
 
+// One cell of the recurrence, for a cell with value `bit` (0 or 1), column height H above it, row
+// run w ending just left of it and dp[i-1][j-1] = dprev: since every term of the minimum gains
+// one when the cell is set,
+//     dp = bit ? 1 + min(H, w, dprev) : 0,    H <- bit ? H + 1 : 0,    w <- bit ? w + 1 : 0,
+// each "bit ? v + 1 : 0" being the 24-bit multiply-add v * bit + bit.  The windowed passes keep
+// every operand below 2^24: heights count the rows of one item (a band plus its halo), runs the
+// columns of one window.
+__device__ __forceinline__ int32_t cell_step(int32_t &H, int32_t &w, int32_t dprev, uint32_t bit) {
+    int32_t m3 = H < w ? H : w;
+    m3 = m3 < dprev ? m3 : dprev;
+    H = (int32_t)(__umul24((uint32_t)H, bit) + bit);
+    w = (int32_t)(__umul24((uint32_t)w, bit) + bit);
+    return (int32_t)(__umul24((uint32_t)m3, bit) + bit);
+}
+
 // ----------------------------------------------------------------------------------------------
 // dprun: dp over rows [rh, rb) x columns [xh, xh + ng * 64 * CPL), zero state above row rh and
 // left of column xh (xh is a multiple of 64).  Lane l of group g owns the CPL consecutive
@@ -225,33 +240,28 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // the words and entering runs of the next row are read before the current row is used
-        uint64_t nx[NGMAX];
-        int32_t ncr[NGMAX];
-#pragma unroll
-        for (int g = 0; g < NGMAX; ++g) {
-            nx[g] = (g < ng) ? lds.x[g * CPL + q] : 0ull;
-            ncr[g] = (g < ng) ? lds.c[g * CPL + q] : 0;
-        }
-        for (int rr = 0; rr < rc; ++rr) {
-            const int64_t i = r0 + rr;
-            const bool own_row = i >= ra;
-            uint64_t cx[NGMAX];
-            int32_t ccr[NGMAX];
+        // rows are walked two at a time through two register sets, so that the next row's
+        // words and entering runs are read from LDS while the current row is computed
+        const auto load_row = [&](int rr, uint64_t (&x)[NGMAX], int32_t (&cr)[NGMAX]) {
 #pragma unroll
             for (int g = 0; g < NGMAX; ++g) {
-                cx[g] = nx[g];
-                ccr[g] = ncr[g];
-            }
-            if (rr + 1 < rc) {
-#pragma unroll
-                for (int g = 0; g < NGMAX; ++g) {
-                    if (g < ng) {
-                        nx[g] = lds.x[(rr + 1) * nww + g * CPL + q];
-                        ncr[g] = lds.c[(rr + 1) * nww + g * CPL + q];
-                    }
+                if (g < ng) {
+                    x[g] = lds.x[rr * nww + g * CPL + q];
+                    cr[g] = lds.c[rr * nww + g * CPL + q];
+                } else {
+                    x[g] = 0ull;
+                    cr[g] = 0;
                 }
             }
+        };
+        // rows of the chunk from own_from on are owned (32-bit, uniform)
+        const int own_from = (int)(ra - r0 > 0 ? (ra - r0 < rc ? ra - r0 : rc) : 0);
+        // common case: 16-byte stores, and every lane owns all or none of its columns (xa is a
+        // multiple of 64, so only a right edge that is not a multiple of CPL splits a lane)
+        const bool whole = vec_ok && (CPL % 4 == 0) && (xb % CPL) == 0;
+        const auto row = [&](int rr, const uint64_t (&cx)[NGMAX], const int32_t (&ccr)[NGMAX]) {
+            const int64_t i = r0 + rr;
+            const bool own_row = rr >= own_from;
             int32_t dleft_old = 0;  // previous-row dp just left of the group
             const int krow = (CLASSED && own_row) ? (int)kq : 0;
             if (CLASSED && ++kr == sc.tile_rows) {
@@ -274,18 +284,21 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                     int32_t w = wrun;
 #pragma unroll
                     for (int t = 0; t < CPL; ++t) {
-                        const int32_t mk = -(int32_t)((nib >> t) & 1u);
-                        const int32_t h = (H[g][t] + 1) & mk;
-                        w = (w + 1) & mk;
                         const int32_t old = D[g][t];
-                        int32_t d = h < w ? h : w;
-                        d = d < dprev + 1 ? d : dprev + 1;
-                        H[g][t] = h;
-                        D[g][t] = d;
+                        D[g][t] = cell_step(H[g][t], w, dprev, (nib >> t) & 1u);
                         dprev = old;
                     }
                     const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;
-                    if (own_row && (!CLASSED || ((sc.cls[g] >> krow) & 1))) {
+                    if (STORE && !TRACK && whole) {
+                        if (own_row && col >= xa && col < xb &&
+                            (!CLASSED || ((sc.cls[g] >> krow) & 1))) {
+                            int32_t *p = dp + i * ld_dp + col;
+#pragma unroll
+                            for (int t = 0; t < CPL; t += 4)
+                                *reinterpret_cast<int4 *>(p + t) =
+                                    make_int4(D[g][t], D[g][t + 1], D[g][t + 2], D[g][t + 3]);
+                        }
+                    } else if (own_row && (!CLASSED || ((sc.cls[g] >> krow) & 1))) {
                         if (STORE) {
                             int32_t *p = dp + i * ld_dp + col;
                             if (col >= xa && col + CPL <= xb) {
@@ -317,6 +330,16 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                     }
                 }
             }
+        };
+        uint64_t rx0[NGMAX], rx1[NGMAX];
+        int32_t rc0[NGMAX], rc1[NGMAX];
+        load_row(0, rx0, rc0);
+        for (int rr = 0; rr < rc; rr += 2) {
+            if (rr + 1 < rc) load_row(rr + 1, rx1, rc1);
+            row(rr, rx0, rc0);
+            if (rr + 1 >= rc) break;
+            if (rr + 2 < rc) load_row(rr + 2, rx0, rc0);
+            row(rr + 1, rx1, rc1);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
@@ -977,14 +1000,8 @@ __device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int6
                     int32_t w = wrun;
 #pragma unroll
                     for (int t = 0; t < CPL; ++t) {
-                        const int32_t mk = -(int32_t)((nib >> t) & 1u);
-                        const int32_t h = (H[gl][t] + 1) & mk;
-                        w = (w + 1) & mk;
                         const int32_t old = D[gl][t];
-                        int32_t d = h < w ? h : w;
-                        d = d < dprev + 1 ? d : dprev + 1;
-                        H[gl][t] = h;
-                        D[gl][t] = d;
+                        D[gl][t] = cell_step(H[gl][t], w, dprev, (nib >> t) & 1u);
                         dprev = old;
                     }
                     const int64_t col = xh + (int64_t)g * GW + (int64_t)lane * CPL;

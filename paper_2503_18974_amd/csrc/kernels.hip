@@ -207,7 +207,8 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
 // every cell when S <= MAP_NARROW_REACH; in region mode (S beyond the reach, per-tile bounds of
 // a search in the same call) the cells of the tiles bounded by REGION_SMALL, with REGION_SMALL
 // halos.  Band height: at least band_rows and 4 S (so the S-row head start costs at most a
-// quarter), halved while that leaves fewer items than min_items, down to 2 S (or 16 rows).
+// quarter), halved while that leaves fewer items than min_items, down to S (or 8 rows): on a
+// small matrix each item's chain of rows is the latency, and shorter bands shorten it.
 template <int NGMAX, int CPL>
 __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int32_t *__restrict__ dp, int64_t ld_dp, int64_t S,
@@ -220,7 +221,7 @@ __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_
     const int64_t hc = (Sg + 63) & ~(int64_t)63;
     int64_t ng = (hc + (4 * hc > 256 ? 4 * hc : 256) + GW - 1) / GW;
     ng = ng < 1 ? 1 : (ng > NGMAX ? NGMAX : ng);
-    const int64_t rmin = 2 * Sg > 16 ? 2 * Sg : 16;
+    const int64_t rmin = Sg > 8 ? Sg : 8;
     // where even the shortest bands leave fewer items than min_items (a small matrix: each
     // wave's sequence of rows is the latency), a window one group narrower halves every row's
     // work, as long as it still leaves a 64-column output
