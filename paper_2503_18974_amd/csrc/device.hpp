@@ -116,6 +116,15 @@ __device__ __forceinline__ Track wave_track(Track t) {
     return Track{best, p};
 }
 
+// Length of the run of ones that ends just left of bit b of the packed word x (LSB first), given
+// `carry`, the run entering x, and lowmask = the bits below b: b - 1 minus the index of the
+// highest zero below b, or b + carry when there is none (the count of leading zeros of an empty
+// mask is 64).
+__device__ __forceinline__ int32_t run_into(uint64_t x, uint64_t lowmask, int b, int32_t carry) {
+    const int32_t lz = (int32_t)__clzll(~x & lowmask);
+    return lz + (b - 64) + (lz == 64 ? carry : 0);
+}
+
 // One cell of the recurrence, for a cell with value `bit` (0 or 1), column height H above it, row
 // run w ending just left of it and dp[i-1][j-1] = dprev: since every term of the minimum gains
 // one when the cell is set,
@@ -184,6 +193,7 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
     const int lane = __lane_id();
     const int q = lane / LPW;           // word of the group holding this lane's columns
     const int b = (lane % LPW) * CPL;   // bit offset of the lane's first column in that word
+    const uint64_t lowmask = (1ull << b) - 1;  // the word's bits left of the lane's columns
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
     const int nww = ng * CPL;                    // window words
@@ -241,17 +251,16 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // rows are walked two at a time through two register sets, so that the next row's
-        // words and entering runs are read from LDS while the current row is computed
+        // words and entering runs are read from LDS while the current row is computed.  The
+        // reads are unconditional (a group past ng rereads group 0, a row past the chunk rereads
+        // its last row; neither is used), so that no branch or register reset sits between a
+        // read and its use and the wait before a row covers only that row's reads.
         const auto load_row = [&](int rr, uint64_t (&x)[NGMAX], int32_t (&cr)[NGMAX]) {
 #pragma unroll
             for (int g = 0; g < NGMAX; ++g) {
-                if (g < ng) {
-                    x[g] = lds.x[rr * nww + g * CPL + q];
-                    cr[g] = lds.c[rr * nww + g * CPL + q];
-                } else {
-                    x[g] = 0ull;
-                    cr[g] = 0;
-                }
+                const int o = rr * nww + (g < ng ? g : 0) * CPL + q;
+                x[g] = lds.x[o];
+                cr[g] = lds.c[o];
             }
         };
         // rows of the chunk from own_from on are owned (32-bit, uniform)
@@ -273,11 +282,7 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
                 if (g < ng) {
                     const uint64_t x = cx[g];
                     const int32_t carry = ccr[g];
-                    int32_t wrun = carry;
-                    if (b != 0) {
-                        const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
-                        wrun = (lo == b) ? b + carry : lo;
-                    }
+                    const int32_t wrun = run_into(x, lowmask, b, carry);
                     const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
                     int32_t dprev = from_left_lane(D[g][CPL - 1], dleft_old);
                     dleft_old = __builtin_amdgcn_readlane(D[g][CPL - 1], WAVE - 1);
@@ -335,10 +340,10 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
         int32_t rc0[NGMAX], rc1[NGMAX];
         load_row(0, rx0, rc0);
         for (int rr = 0; rr < rc; rr += 2) {
-            if (rr + 1 < rc) load_row(rr + 1, rx1, rc1);
+            load_row(rr + 1 < rc ? rr + 1 : rr, rx1, rc1);
             row(rr, rx0, rc0);
             if (rr + 1 >= rc) break;
-            if (rr + 2 < rc) load_row(rr + 2, rx0, rc0);
+            load_row(rr + 2 < rc ? rr + 2 : rr + 1, rx0, rc0);
             row(rr + 1, rx1, rc1);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -919,6 +924,7 @@ __device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int6
     const int wv = tid / WAVE, lane = tid % WAVE;
     const int q = lane / LPW;
     const int b = (lane % LPW) * CPL;
+    const uint64_t lowmask = (1ull << b) - 1;
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
     const int nww = ng * CPL;
@@ -989,11 +995,7 @@ __device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int6
                 if (g < ng) {
                     const uint64_t x = L.x[rr * nww + g * CPL + q];
                     const int32_t carry = L.c[rr * nww + g * CPL + q];
-                    int32_t wrun = carry;
-                    if (b != 0) {
-                        const int32_t lo = (int32_t)__clzll(~(x << (64 - b)));
-                        wrun = (lo == b) ? b + carry : lo;
-                    }
+                    const int32_t wrun = run_into(x, lowmask, b, carry);
                     const uint32_t nib = (uint32_t)(x >> b) & ((1u << CPL) - 1u);
                     int32_t dprev = from_left_lane(D[gl][CPL - 1], dleft_old);
                     dleft_old = __builtin_amdgcn_readlane(D[gl][CPL - 1], WAVE - 1);
