@@ -208,13 +208,15 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
 // a search in the same call) the cells of the tiles bounded by REGION_SMALL, with REGION_SMALL
 // halos.  Band height: at least band_rows and 4 S (so the S-row head start costs at most a
 // quarter), halved while that leaves fewer items than min_items, down to S (or 8 rows): on a
-// small matrix each item's chain of rows is the latency, and shorter bands shorten it.
+// small matrix each item's chain of rows is the latency, and shorter bands shorten it.  Items go
+// to waves wave, wave + nwave, ... (the caller's numbering of the waves taking part).
 template <int NGMAX, int CPL>
 __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int32_t *__restrict__ dp, int64_t ld_dp, int64_t S,
                             int64_t band_rows, int vec_ok, bool region,
                             const int32_t *__restrict__ bounds, int64_t tile_rows,
-                            int64_t tile_ntx, int64_t min_items, WaveLds lds) {
+                            int64_t tile_ntx, int64_t min_items, WaveLds lds, int64_t wave,
+                            int64_t nwave) {
     constexpr int64_t GW = 64 * CPL;
     constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
     const int64_t Sg = region ? REGION_SMALL : S;  // the side the halos must cover
@@ -230,8 +232,6 @@ __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_
         ng -= 1;
     const int64_t ow = ng * GW - hc;
     const int64_t nwin = (n + ow - 1) / ow;
-    const int64_t wave = wave_index();
-    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     // the tallest bands (the least halo work) that still leave min_items items
     int64_t R = band_rows > 4 * Sg ? band_rows : 4 * Sg;
     while (R > rmin && ((m + R - 1) / R) * nwin < min_items) R = (R / 2 > rmin) ? R / 2 : rmin;
@@ -282,8 +282,9 @@ __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_
 // The wide pass of the map (MAP_NARROW_REACH < S <= 1984): windows of 2048 columns, one window
 // per block (dprun_block), items distributed per block so that the block's barriers stay
 // uniform.  In region mode only the cells of tiles bounded above REGION_SMALL (or saturated) are
-// stored, with S halos.  Beyond 1984 one wave sweeps the whole matrix.
-__device__ void wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+// stored, with S halos, and the pass returns how many items it dealt (the k-th to block
+// k mod gridDim.x).  Beyond 1984 one wave sweeps the whole matrix.
+__device__ int64_t wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                           int32_t *__restrict__ dp, int64_t ld_dp, int64_t S, int64_t band_rows,
                           int32_t *serial_state, int vec_ok, bool region,
                           const int32_t *__restrict__ bounds, int64_t tile_rows,
@@ -297,7 +298,7 @@ __device__ void wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t 
             Track tr{0, INT64_MAX};
             serial_dp<true>(bits, m, n, ldw, dp, ld_dp, serial_state, serial_state + nw64, tr);
         }
-        return;
+        return 0;
     }
     const int64_t ow = WIN - hc;
     const int64_t nwin = (n + ow - 1) / ow;
@@ -324,7 +325,7 @@ __device__ void wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t 
             dprun_block<false>(bits, ldw, n, rh, ra, rb, xh, xa, xb, ngi, dp, ld_dp, vec_ok != 0,
                                L, StoreClass<2>{});
         }
-        return;
+        return 0;
     }
     // Region mode: only items touching a tile bounded above REGION_SMALL (or saturated) have
     // cells to store, and they cluster around the large squares, so dealing items to blocks by
@@ -392,6 +393,7 @@ __device__ void wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t 
         before += ctotal;
         __syncthreads();  // the next round rewrites s_cnt, s_nsel and s_sel
     }
+    return before;  // the items dealt, the same count in every block
 }
 
 // ---------------------------------------------------------------------------------- map
@@ -418,15 +420,27 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
     __shared__ int32_t lslot[8];
     const int64_t S = uniform(maxsq->side);
     const bool region = bounds != nullptr && S > MAP_NARROW_REACH;
-    if (S <= MAP_NARROW_REACH || region) {
-        const int wv = threadIdx.x / WAVE;
-        narrow_pass<NGMAX, CPL>(bits, m, n, ldw, dp, ld_dp, S, band_rows, vec_ok, region, bounds,
-                                tile_rows, tile_ntx, min_items,
-                                WaveLds{lx + wv * LDSW, lc + wv * LDSW, LDSW});
-    }
-    if (S > MAP_NARROW_REACH) {
-        __syncthreads();  // the wide pass takes the block's LDS as one region
-        wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state, vec_ok, region, bounds,
+    const int wv = threadIdx.x / WAVE;
+    const WaveLds wave_lds{lx + wv * LDSW, lc + wv * LDSW, LDSW};
+    const int64_t nblk = gridDim.x;
+    if (region) {
+        // The block-wide items are long chains (S + R rows each) and few: they start first, and
+        // the blocks holding one take no one-wave item, which the other blocks share.
+        const int64_t dealt = wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state,
+                                        vec_ok, true, bounds, tile_rows, tile_ntx,
+                                        BlockLds{lx, lc, lslot});
+        const int64_t busy = dealt < nblk ? dealt : 0;  // blocks 0 .. busy-1 held a chain
+        if ((int64_t)blockIdx.x < busy) return;
+        __syncthreads();  // the narrow pass takes the block's LDS as four per-wave regions
+        narrow_pass<NGMAX, CPL>(bits, m, n, ldw, dp, ld_dp, S, band_rows, vec_ok, true, bounds,
+                                tile_rows, tile_ntx, min_items, wave_lds,
+                                ((int64_t)blockIdx.x - busy) * 4 + wv, (nblk - busy) * 4);
+    } else if (S <= MAP_NARROW_REACH) {
+        narrow_pass<NGMAX, CPL>(bits, m, n, ldw, dp, ld_dp, S, band_rows, vec_ok, false, bounds,
+                                tile_rows, tile_ntx, min_items, wave_lds, wave_index(),
+                                nblk * 4);
+    } else {
+        wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state, vec_ok, false, bounds,
                   tile_rows, tile_ntx, BlockLds{lx, lc, lslot});
     }
 }

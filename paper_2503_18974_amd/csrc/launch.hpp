@@ -48,7 +48,7 @@ hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *
                              uint8_t *sat, int32_t *bounds, ms_square *out);
 int64_t max_probe_tiles(int64_t m, int64_t n);
 
-// The narrow map kernel shortens its row bands (and narrows its window) until it has at least
+// The map's narrow pass shortens its row bands (and narrows its window) until it has at least
 // this many items per SIMD (4 SIMDs per CU), or reaches its shortest band.
 constexpr int MAP_ITEMS_PER_SIMD = 2;
 
