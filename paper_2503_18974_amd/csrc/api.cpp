@@ -347,7 +347,8 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
     mshost::LaunchEnv env{c->num_cus, st};
     // the search just ran on these bits: its per-tile bounds let the map size halos by region
     const mshost::MapRegions regions{bounds_of(c), mshost::probe_tile_rows(cfg.probe_variant),
-                                     cdiv(cdiv(n, 64), mshost::PROBE_TILE_WORDS)};
+                                     cdiv(cdiv(n, 64), mshost::PROBE_TILE_WORDS),
+                                     hdr_of(c)->big_box};
     hipError_t e = mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m, n,
                                              ld_words, d_dp, ld_dp, &hdr_of(c)->result,
                                              state_of(c), &regions);

@@ -499,15 +499,20 @@ struct TileSink {
 // replaces).  Written with one store per array per 64 tiles: a store per tile would make the
 // next tile's loads wait for it.
 constexpr int32_t SAT_BOUND = -1;
-// Largest side the narrow dp-map kernel (512-column windows) covers.
+// Largest side the dp map's narrow pass (512-column windows) covers.
 constexpr int32_t MAP_NARROW_REACH = 448;
 // When a square exceeds that reach, the map is split by tile: tiles bounded by REGION_SMALL are
-// mapped by the narrow kernel with a REGION_SMALL halo, the others by the wide kernel.
+// mapped by the narrow pass with a REGION_SMALL halo, the others by the block-wide pass.
 constexpr int32_t REGION_SMALL = 64;
+
+// Encoding of a tile row or column as the low corner of a bounding box kept with atomicMax.
+constexpr uint32_t BOX_LOW = 1u << 30;
 
 struct SatBatch {
     uint8_t *base;
     int32_t *bounds = nullptr;
+    uint32_t *box = nullptr;   // with bounds: the box of tiles bounded above REGION_SMALL
+    int64_t ntx = 1;           // tiles per tile row (for the box)
     int64_t t0 = 0, stride = 1;
     uint64_t bits = 0;
     int count = 0, nsat = 0;
@@ -526,6 +531,21 @@ struct SatBatch {
         if (lane < count) {
             base[t0 + lane * stride] = (uint8_t)((bits >> lane) & 1);
             if (bounds) bounds[t0 + lane * stride] = mine;
+        }
+        const bool big = bounds && lane < count && (mine < 0 || mine > REGION_SMALL);
+        if (box && __ballot(big)) {
+            const int64_t t = t0 + lane * stride;
+            const int64_t ty = t / ntx, tx = t - ty * ntx;
+            const int32_t e0 = wave_max_i32(big ? (int32_t)(BOX_LOW - (uint32_t)ty) : 0);
+            const int32_t e1 = wave_max_i32(big ? (int32_t)(ty + 1) : 0);
+            const int32_t e2 = wave_max_i32(big ? (int32_t)(BOX_LOW - (uint32_t)tx) : 0);
+            const int32_t e3 = wave_max_i32(big ? (int32_t)(tx + 1) : 0);
+            if (lane == 0) {
+                atomicMax(&box[0], (uint32_t)e0);
+                atomicMax(&box[1], (uint32_t)e1);
+                atomicMax(&box[2], (uint32_t)e2);
+                atomicMax(&box[3], (uint32_t)e3);
+            }
         }
         bits = 0;
         count = 0;

@@ -102,6 +102,8 @@ __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     SatBatch sb{sat};
     sb.bounds = bounds;
+    sb.box = bounds ? hdr->big_acc : nullptr;
+    sb.ntx = ntx;
     sb.stride = nwave;
     for (int64_t t = wave; t < ntiles; t += nwave) {
         const int64_t ty = t / ntx, tx = t - ty * ntx;
@@ -148,6 +150,11 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
         hdr->serial_flag = 0;
         hdr->nsat = 0;
         hdr->done = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            hdr->big_box[k] = load_relaxed_u32(&hdr->big_acc[k]);
+            hdr->big_acc[k] = 0;
+        }
     }
 }
 
@@ -288,7 +295,7 @@ __device__ int64_t wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64
                           int32_t *__restrict__ dp, int64_t ld_dp, int64_t S, int64_t band_rows,
                           int32_t *serial_state, int vec_ok, bool region,
                           const int32_t *__restrict__ bounds, int64_t tile_rows,
-                          int64_t tile_ntx, BlockLds L) {
+                          int64_t tile_ntx, BlockLds L, const uint32_t *box) {
     constexpr int64_t GW = 256, NGB = 8, WIN = NGB * GW, REACH = WIN - 64;
     constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
     const int64_t hc = (S + 63) & ~(int64_t)63;
@@ -330,16 +337,32 @@ __device__ int64_t wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64
     // Region mode: only items touching a tile bounded above REGION_SMALL (or saturated) have
     // cells to store, and they cluster around the large squares, so dealing items to blocks by
     // index would stack several on one block.  Every block instead ranks those items in item
-    // order (a pass over all items, 256 per round: a ballot per wave and the four wave counts)
-    // and maps the ones whose rank is its index modulo the grid.
+    // order (256 per round: a ballot per wave and the four wave counts) and maps the ones whose
+    // rank is its index modulo the grid.  Only the items meeting the search's bounding box of
+    // such tiles are ranked: bands kb0..kb1 and windows kw0..kw1, in item order.
+    const uint32_t e0 = box[0], e1 = box[1], e2 = box[2], e3 = box[3];
+    if (e1 == 0) return 0;  // no tile beyond the narrow pass's halo
+    const int64_t ty_lo = (int64_t)(BOX_LOW - e0), ty_hi = (int64_t)e1 - 1;
+    const int64_t tx_lo = (int64_t)(BOX_LOW - e2), tx_hi = (int64_t)e3 - 1;
+    const int64_t nbands = (m + R - 1) / R;
+    const int64_t kb0 = ty_lo * tile_rows / R;
+    int64_t kb1 = ((ty_hi + 1) * tile_rows - 1) / R;
+    kb1 = kb1 < nbands - 1 ? kb1 : nbands - 1;
+    const int64_t kw0 = tx_lo * TILE_COLS / ow;
+    int64_t kw1 = ((tx_hi + 1) * TILE_COLS - 1) / ow;
+    kw1 = kw1 < nwin - 1 ? kw1 : nwin - 1;
+    const int64_t bw = kw1 - kw0 + 1;
+    const int64_t boxed = (kb1 - kb0 + 1) * bw;
     __shared__ int32_t s_cnt[4];
     __shared__ int32_t s_nsel;
     __shared__ int64_t s_sel[256];
     int64_t before = 0;  // active items in earlier rounds (the same in every thread)
-    for (int64_t c0 = 0; c0 < items; c0 += 256) {
-        const int64_t it = c0 + threadIdx.x;
+    for (int64_t c0 = 0; c0 < boxed; c0 += 256) {
+        const int64_t bi = c0 + threadIdx.x;  // index among the boxed items
+        const int64_t kb = bi / bw;
+        const int64_t it = (kb0 + kb) * nwin + kw0 + (bi - kb * bw);
         bool act = false;
-        if (it < items) {
+        if (bi < boxed) {
             const int64_t bnd_i = it / nwin, wdx = it - bnd_i * nwin;
             const int64_t ra = bnd_i * R, rb = ra + R < m ? ra + R : m;
             const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
@@ -412,7 +435,7 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
                                                int64_t band_rows, int32_t *serial_state,
                                                int vec_ok, const int32_t *__restrict__ bounds,
                                                int64_t tile_rows, int64_t tile_ntx,
-                                               int64_t min_items) {
+                                               const uint32_t *big_box, int64_t min_items) {
     constexpr int LDSW = BLK_WORDS / 4;  // words per wave in the narrow pass
     static_assert(NGMAX * CPL * 64 <= LDSW, "a row chunk holds at least 64 rows");
     __shared__ uint64_t lx[BLK_WORDS];
@@ -428,7 +451,7 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
         // the blocks holding one take no one-wave item, which the other blocks share.
         const int64_t dealt = wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state,
                                         vec_ok, true, bounds, tile_rows, tile_ntx,
-                                        BlockLds{lx, lc, lslot});
+                                        BlockLds{lx, lc, lslot}, big_box);
         const int64_t busy = dealt < nblk ? dealt : 0;  // blocks 0 .. busy-1 held a chain
         if ((int64_t)blockIdx.x < busy) return;
         __syncthreads();  // the narrow pass takes the block's LDS as four per-wave regions
@@ -441,7 +464,7 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
                                 nblk * 4);
     } else {
         wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state, vec_ok, false, bounds,
-                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot});
+                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot}, nullptr);
     }
 }
 
@@ -869,17 +892,18 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
     const int32_t *bounds = regions ? regions->bounds : nullptr;
     const int64_t trows = regions ? regions->tile_rows : 1;
     const int64_t tntx = regions ? regions->tile_ntx : 1;
+    const uint32_t *box = regions ? regions->big_box : nullptr;
     const int64_t min_items = (int64_t)env.num_cus * 4 * MAP_ITEMS_PER_SIMD;
     // one kernel: the narrow pass (512-column windows as 2 x 4 or 1 x 8 columns per lane) and,
     // for squares beyond its reach, the block-wide pass
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
-                           min_items);
+                           box, min_items);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
-                           min_items);
+                           box, min_items);
     }
     return hipGetLastError();
 }

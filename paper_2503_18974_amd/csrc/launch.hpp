@@ -18,9 +18,16 @@ struct ScratchHeader {
     ms_square result;           // last result (read by the map pass)
     uint32_t done;              // waves of the resolve pass that have finished
     uint32_t pad0;
-    uint64_t pad1[2];
+    // Bounding box of the probe tiles whose largest side may exceed the narrow map's region
+    // halo (bound above REGION_SMALL, or saturated), as {2^30 - first tile row, last tile row
+    // + 1, 2^30 - first tile column, last tile column + 1}, all zero when there is none:
+    // gathered by the probe with atomicMax, handed to the map (big_box) and cleared by the
+    // wave that writes the result.
+    uint32_t big_acc[4];
+    uint32_t big_box[4];
+    uint64_t pad1[6];
 };
-static_assert(sizeof(ScratchHeader) == 64, "header layout");
+static_assert(sizeof(ScratchHeader) == 128, "header layout");
 
 // Erosion tile variants compiled into the library.
 struct ProbeVariant {
@@ -57,6 +64,7 @@ struct MapRegions {
     const int32_t *bounds;     // one per probe tile: an upper bound on its largest side, or -1
     int64_t tile_rows;         // the probe variant's owned rows per tile
     int64_t tile_ntx;          // tiles per tile row
+    const uint32_t *big_box;   // ScratchHeader::big_box of that search
 };
 
 // dp map of one matrix; reads S from *maxsq on the device (a largest-square result).  With
