@@ -141,14 +141,19 @@ int bucket_of(int64_t m, int64_t n) {
     return lg(m) * 64 + lg(n);
 }
 
-// Untuned matrices of at least this many cells take the probe tile certifying side 32: on the
+// Untuned matrices of at least LARGE_CELLS cells take the probe tile certifying side 32: on the
 // large matrices more tiles then finish in the probe and fewer go to the resolve pass (a 16384^2
 // blob image: 441 instead of 543 us; a 32768^2 Bernoulli(0.9) matrix: 124 instead of 119 us).
+// Below SMALL_CELLS the search is latency-bound (a 4000^2 matrix fills a tenth of the device's
+// waves with 113-row tiles), and the 49-row tile, twice the tiles for half the chain each, is
+// faster (1000^2: 10.1 instead of 12.5 us; 4000^2: 13.5 instead of 14.0 us).
 constexpr int64_t LARGE_CELLS = int64_t(1) << 26;
+constexpr int64_t SMALL_CELLS = int64_t(1) << 24;
 
 ms_config default_config(int64_t m, int64_t n) {
     ms_config c = DEFAULT_CONFIG;
     if (m > 0 && n > 0 && m >= LARGE_CELLS / n) c.probe_variant = 2;
+    if (m > 0 && n > 0 && m < SMALL_CELLS / n) c.probe_variant = 0;
     return c;
 }
 

@@ -114,6 +114,21 @@ def test_candidates_and_config_validation():
     assert L.ms_candidate(n, ctypes.byref(M._Config())) == INVALID
 
 
+def test_default_config_by_size():
+    """Untuned defaults (no context: host only): the 49-row probe tile below 2^24 cells, the
+    113-row 16-certified tile up to 2^26, the 32-certified tile from there on."""
+    def variant(m, n):
+        return M.ms_get_config(None, m, n)["probe_variant"]
+    assert variant(1000, 1000) == 0
+    assert variant(4096, 4095) == 0
+    assert variant(4096, 4096) == 1
+    assert variant(5000, 5000) == 1
+    assert variant(8191, 8192) == 1
+    assert variant(8192, 8192) == 2
+    assert variant(4096, 262144) == 2
+    assert M.ms_get_config(None, 5000, 5000)["map_cols"] == 4
+
+
 def test_create_rejects_bad_args():
     L = M.lib()
     assert L.ms_create(None, 0) == INVALID
