@@ -861,7 +861,7 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
                              int64_t ldw, int64_t ty, int64_t tx, int64_t ntx,
                              const uint8_t *__restrict__ sat, unsigned long long *key,
                              uint32_t *serial_flag, int32_t *bounds = nullptr, int part = 0,
-                             int nparts = 1) {
+                             int nparts = 1, uint32_t *serial_count = nullptr) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
     m = uniform(m);
@@ -895,7 +895,9 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
         int32_t best = 0;
         int64_t bpos = 0;
         if (!resolve_pass<TS>(bits, m, n, ldw, ra, rb, tx, U, &best, &bpos)) {
-            if (lane == 0) atomicOr(serial_flag, 1u);  // the serial pass finishes the matrix
+            // the serial pass finishes the matrix; serial_count counts the matrices so flagged
+            if (lane == 0 && atomicOr(serial_flag, 1u) == 0u && serial_count)
+                atomicAdd(serial_count, 1u);
             return;
         }
         best = uniform(best);

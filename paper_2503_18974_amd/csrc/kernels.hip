@@ -477,9 +477,10 @@ __global__ void k_write_result(ms_square *out, mshost::ScratchHeader *hdr, int64
 
 // ---------------------------------------------------------------------------------- batched
 struct BatchCounters {
-    uint32_t error;   // bit 1: the device prefix disagrees with the host's tile count
-    uint32_t nsat;    // saturated tiles over the whole batch
-    uint32_t pad[6];
+    uint32_t error;    // bit 1: the device prefix disagrees with the host's tile count
+    uint32_t nsat;     // saturated tiles over the whole batch
+    uint32_t nserial;  // matrices flagged for the serial pass
+    uint32_t pad[5];
 };
 
 // One block: clear per-matrix keys and flags, exclusive prefix of tile counts.
@@ -525,6 +526,7 @@ __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict
         prefix[count] = part[1023];
         ctr->error = 0;
         ctr->nsat = 0;
+        ctr->nserial = 0;
     }
 }
 
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(256) void k_batch_resolve(const ms_matrix *__restri
                                                        unsigned long long *__restrict__ keys,
                                                        const uint64_t *__restrict__ prefix,
                                                        uint32_t *__restrict__ flags,
-                                                       const BatchCounters *ctr,
+                                                       BatchCounters *ctr,
                                                        const uint8_t *__restrict__ sat,
                                                        uint64_t total) {
     const int lane = __lane_id();
@@ -600,13 +602,14 @@ __global__ __launch_bounds__(256) void k_batch_resolve(const ms_matrix *__restri
             const int64_t t = (int64_t)(item - prefix[mi]);
             const int64_t ty = t / ntx, tx = t - ty * ntx;
             resolve_tile<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
-                             keys + mi, flags + mi);
+                             keys + mi, flags + mi, nullptr, 0, 1, &ctr->nserial);
         }
     }
 }
 
-// Key -> result per matrix; matrices with a square too wide for the windowed pass are finished
-// by block 0 with the serial pass (it owns the state buffer).
+// Key -> result per matrix, one matrix per thread; matrices with a square too wide for the
+// windowed pass are finished by block 0 with the serial pass (it owns the state buffer), found
+// 64 at a time by a ballot, and only when the resolve pass flagged any.
 __global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict__ mats,
                                                     int64_t count,
                                                     const unsigned long long *__restrict__ keys,
@@ -614,27 +617,37 @@ __global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict_
                                                     const BatchCounters *ctr,
                                                     int32_t *serial_state, ms_square *out) {
     const int lane = __lane_id();
+    const int64_t stride = (int64_t)gridDim.x * WAVE;
     if (load_relaxed_u32(&ctr->error) & 2u) {  // inconsistent batch: report every result failed
-        for (int64_t i = blockIdx.x; i < count; i += gridDim.x)
-            if (lane == 0) out[i] = ms_square{-1, -1, -1};
+        for (int64_t i = (int64_t)blockIdx.x * WAVE + lane; i < count; i += stride)
+            out[i] = ms_square{-1, -1, -1};
         return;
     }
-    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * WAVE + lane; i < count; i += stride) {
         const ms_matrix d = mats[i];
         const bool serial = d.m > 0 && d.n > 0 && load_relaxed_u32(flags + i);
-        if (!serial && lane == 0) write_result(load_relaxed(keys + i), d.n, out + i);
+        if (!serial) write_result(load_relaxed(keys + i), d.n, out + i);
     }
-    if (blockIdx.x != 0) return;
-    for (int64_t i = 0; i < count; ++i) {
-        const ms_matrix d = mats[i];
-        if (!(d.m > 0 && d.n > 0 && load_relaxed_u32(flags + i))) continue;
-        const int64_t nw64 = ((d.n + 63) >> 6) * 64;
-        Track tr{0, INT64_MAX};
-        serial_dp<false>(d.bits, d.m, d.n, d.ld_words, nullptr, 0, serial_state,
-                         serial_state + nw64, tr);
-        const Track w = wave_track(tr);
-        const unsigned long long key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
-        if (lane == 0) write_result(key, d.n, out + i);
+    if (blockIdx.x != 0 || load_relaxed_u32(&ctr->nserial) == 0) return;
+    for (int64_t b0 = 0; b0 < count; b0 += WAVE) {
+        bool flagged = false;
+        if (b0 + lane < count) {
+            const ms_matrix d = mats[b0 + lane];
+            flagged = d.m > 0 && d.n > 0 && load_relaxed_u32(flags + b0 + lane);
+        }
+        uint64_t todo = __ballot(flagged);
+        while (todo) {
+            const int64_t i = b0 + __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const ms_matrix d = mats[i];
+            const int64_t nw64 = ((d.n + 63) >> 6) * 64;
+            Track tr{0, INT64_MAX};
+            serial_dp<false>(d.bits, d.m, d.n, d.ld_words, nullptr, 0, serial_state,
+                             serial_state + nw64, tr);
+            const Track w = wave_track(tr);
+            const unsigned long long key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
+            if (lane == 0) write_result(key, d.n, out + i);
+        }
     }
 }
 
@@ -974,7 +987,8 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
                        env.stream, mats, count, keys, prefix, flags, ctr, sat,
                        (uint64_t)L.total_tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t fb = std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)env.num_cus * 4));
+    const int64_t fb = std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 64),
+                                                               (int64_t)env.num_cus * 4));
     hipLaunchKernelGGL(msk::k_batch_final, dim3((unsigned)fb), dim3(64), 0, env.stream, mats,
                        count, keys, flags, ctr, state, out);
     return hipGetLastError();

@@ -50,10 +50,29 @@ def test_batched_edges(dev):
 
 
 def test_batched_large_square_serial_path(dev):
-    """A square wider than the exact pass's window goes through the serial pass."""
+    """A square far beyond the erosion tile's certified side (the resolve pass bounds it by the
+    runs of saturated tiles and takes it in one window of 33 words)."""
     announce("batched serial")
     mats = [np.ones((2100, 2050), np.uint8), W.gen_bernoulli(500, 500, 0.7, 5)]
     check_batch(mats, dev)
+
+
+def test_batched_serial_flags_spread(dev):
+    """Serial-pass matrices in different 64-matrix groups of a larger batch (the final kernel
+    finds them by a ballot per group), run twice on one workspace (the count is cleared)."""
+    announce("batched serial spread")
+    mats = make_mix(6, 150)
+    # 66 words per row: the resolve window of the right-most tiles outgrows one word per lane
+    for k, i in enumerate((5, 70, 149)):
+        big = np.ones((4200, 4200), np.uint8)
+        big[4199 - 300 * k, 4199 - 7 * k] = 0
+        mats[i] = big
+    items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
+    b = M.Batch(items)
+    refs = [oracle.max_square(a) for a in mats]
+    for _ in range(2):
+        b.run()
+        assert [(g.side, g.row, g.col) for g in b.results()] == refs
 
 
 def test_batched_order_and_duplicates(dev):
