@@ -146,20 +146,18 @@ int bucket_of(int64_t m, int64_t n) {
 // blob image: 441 instead of 543 us; a 32768^2 Bernoulli(0.9) matrix: 124 instead of 119 us).
 // Below SMALL_CELLS the search is latency-bound (a 4000^2 matrix fills a tenth of the device's
 // waves with 113-row tiles), and the 49-row tile, twice the tiles for half the chain each, is
-// faster (1000^2: 10.1 instead of 12.5 us; 4000^2: 13.5 instead of 14.0 us).  There the map's
-// lanes also take 8 columns each (one entering-run computation per 8 cells instead of 4):
-// 2000^2 11.2 instead of 12.5 us, 3000^2 14.8 instead of 15.9; from 5000^2 on, 4 columns per
-// lane (two groups per window) are faster again (24.3 against 25.5 us).
+// faster (1000^2: 10.1 instead of 12.5 us; 4000^2: 13.5 instead of 14.0 us).  The map keeps 4
+// columns per lane: 8 (one entering-run computation per 8 cells) is faster for one map alone
+// (2000^2: 11.2 instead of 12.5 us) but its 32-byte lane strides make each store instruction
+// touch twice the cache lines, and with maps of several streams in flight the grid step drops
+// (541 against 568 Gcells/s).
 constexpr int64_t LARGE_CELLS = int64_t(1) << 26;
 constexpr int64_t SMALL_CELLS = int64_t(1) << 24;
 
 ms_config default_config(int64_t m, int64_t n) {
     ms_config c = DEFAULT_CONFIG;
     if (m > 0 && n > 0 && m >= LARGE_CELLS / n) c.probe_variant = 2;
-    if (m > 0 && n > 0 && m < SMALL_CELLS / n) {
-        c.probe_variant = 0;
-        c.map_cols = 8;
-    }
+    if (m > 0 && n > 0 && m < SMALL_CELLS / n) c.probe_variant = 0;
     return c;
 }
 

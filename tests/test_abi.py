@@ -127,7 +127,7 @@ def test_default_config_by_size():
     assert variant(8192, 8192) == 2
     assert variant(4096, 262144) == 2
     assert M.ms_get_config(None, 5000, 5000)["map_cols"] == 4
-    assert M.ms_get_config(None, 1000, 1000)["map_cols"] == 8
+    assert M.ms_get_config(None, 1000, 1000)["map_cols"] == 4
     assert M.ms_get_config(None, 1000, 1000) in [M.ms_candidate(i)
                                                  for i in range(M.ms_num_candidates())]
 
