@@ -188,9 +188,12 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     }
     const int64_t words = std::max<int64_t>(nwords, c->state_words);
     const int64_t sat = std::max<int64_t>(tiles, c->sat_bytes);
-    // header | serial state | saturation bytes | per-tile bounds (int32)
+    // header | serial state | saturation bytes | per-tile bounds (int32) | probe box records
     const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t) +
-                         (((size_t)sat + 255) & ~(size_t)255) + (size_t)sat * sizeof(int32_t);
+                         (((size_t)sat + 255) & ~(size_t)255) +
+                         (((size_t)sat * sizeof(int32_t) + 255) & ~(size_t)255) +
+                         (size_t)mshost::max_probe_blocks(c->num_cus) *
+                             mshost::BOX_RECORD_WORDS * sizeof(uint32_t);
     if (c->scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
@@ -217,6 +220,11 @@ uint8_t *sat_of(ms_ctx *c) {
 }
 int32_t *bounds_of(ms_ctx *c) {
     return reinterpret_cast<int32_t *>(sat_of(c) + (((size_t)c->sat_bytes + 255) & ~(size_t)255));
+}
+uint32_t *box_records_of(ms_ctx *c) {
+    return reinterpret_cast<uint32_t *>(
+        reinterpret_cast<char *>(bounds_of(c)) +
+        (((size_t)c->sat_bytes * sizeof(int32_t) + 255) & ~(size_t)255));
 }
 int32_t *state_of(ms_ctx *c) {
     return reinterpret_cast<int32_t *>(static_cast<char *>(c->scratch) +
@@ -245,7 +253,8 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
         e = mshost::launch_write_result(env, out, hdr_of(c), out ? 1 : 0);
     } else {
         e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
-                                      state_of(c), sat_of(c), bounds_of(c), out);
+                                      state_of(c), sat_of(c), bounds_of(c), box_records_of(c),
+                                      out);
     }
     if (e != hipSuccess) {
         c->dirty = true;

@@ -511,8 +511,9 @@ constexpr uint32_t BOX_LOW = 1u << 30;
 struct SatBatch {
     uint8_t *base;
     int32_t *bounds = nullptr;
-    uint32_t *box = nullptr;   // with bounds: the box of tiles bounded above REGION_SMALL
+    bool want_box = false;     // with bounds: keep the box of tiles bounded above REGION_SMALL
     int64_t ntx = 1;           // tiles per tile row (for the box)
+    uint32_t box[4] = {0, 0, 0, 0};  // the wave's box so far (wave-uniform; BOX_LOW encoding)
     int64_t t0 = 0, stride = 1;
     uint64_t bits = 0;
     int count = 0, nsat = 0;
@@ -532,20 +533,17 @@ struct SatBatch {
             base[t0 + lane * stride] = (uint8_t)((bits >> lane) & 1);
             if (bounds) bounds[t0 + lane * stride] = mine;
         }
-        const bool big = bounds && lane < count && (mine < 0 || mine > REGION_SMALL);
-        if (box && __ballot(big)) {
+        const bool big = want_box && lane < count && (mine < 0 || mine > REGION_SMALL);
+        if (want_box && __ballot(big)) {
             const int64_t t = t0 + lane * stride;
             const int64_t ty = t / ntx, tx = t - ty * ntx;
-            const int32_t e0 = wave_max_i32(big ? (int32_t)(BOX_LOW - (uint32_t)ty) : 0);
-            const int32_t e1 = wave_max_i32(big ? (int32_t)(ty + 1) : 0);
-            const int32_t e2 = wave_max_i32(big ? (int32_t)(BOX_LOW - (uint32_t)tx) : 0);
-            const int32_t e3 = wave_max_i32(big ? (int32_t)(tx + 1) : 0);
-            if (lane == 0) {
-                atomicMax(&box[0], (uint32_t)e0);
-                atomicMax(&box[1], (uint32_t)e1);
-                atomicMax(&box[2], (uint32_t)e2);
-                atomicMax(&box[3], (uint32_t)e3);
-            }
+            const uint32_t e[4] = {
+                (uint32_t)wave_max_i32(big ? (int32_t)(BOX_LOW - (uint32_t)ty) : 0),
+                (uint32_t)wave_max_i32(big ? (int32_t)(ty + 1) : 0),
+                (uint32_t)wave_max_i32(big ? (int32_t)(BOX_LOW - (uint32_t)tx) : 0),
+                (uint32_t)wave_max_i32(big ? (int32_t)(tx + 1) : 0)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) box[k] = e[k] > box[k] ? e[k] : box[k];
         }
         bits = 0;
         count = 0;

@@ -97,12 +97,13 @@ __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits
                                                int64_t n, int64_t ldw, int64_t ntiles,
                                                int64_t ntx, mshost::ScratchHeader *hdr,
                                                uint8_t *__restrict__ sat,
-                                               int32_t *__restrict__ bounds) {
+                                               int32_t *__restrict__ bounds,
+                                               uint32_t *__restrict__ box_rec) {
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     SatBatch sb{sat};
     sb.bounds = bounds;
-    sb.box = bounds ? hdr->big_acc : nullptr;
+    sb.want_box = box_rec != nullptr;
     sb.ntx = ntx;
     sb.stride = nwave;
     for (int64_t t = wave; t < ntiles; t += nwave) {
@@ -111,6 +112,26 @@ __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits
     }
     sb.flush();
     if (__lane_id() == 0 && sb.nsat) atomicAdd(&hdr->nsat, (uint32_t)sb.nsat);
+    if (box_rec) {
+        // the block's box, one record per block (no atomics: many blocks can hold large
+        // tiles, and same-address atomics from thousands of waves cost more than the search)
+        __shared__ uint32_t s_box[4][4];
+        const int wv = threadIdx.x / WAVE;
+        if (__lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_box[wv][k] = sb.box[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k] = s_box[0][k];
+                for (int w = 1; w < 4; ++w) v[k] = s_box[w][k] > v[k] ? s_box[w][k] : v[k];
+            }
+            reinterpret_cast<uint4 *>(box_rec)[blockIdx.x] = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+    }
 }
 
 __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) {
@@ -131,8 +152,37 @@ __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) 
 // clear the header for the next call.
 __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
                               int64_t ldw, mshost::ScratchHeader *hdr, int32_t *serial_state,
-                              ms_square *out) {
+                              ms_square *out, const uint32_t *__restrict__ box_rec,
+                              int64_t nrec) {
     const int lane = __lane_id();
+    if (box_rec) {
+        // fold the probe blocks' box records for the map of the same call
+        // 16-byte records, eight per lane in flight at a time
+        static_assert(mshost::BOX_RECORD_WORDS == 4, "one uint4 per record");
+        const uint4 *rec = reinterpret_cast<const uint4 *>(box_rec);
+        uint32_t b[4] = {0, 0, 0, 0};
+        for (int64_t i0 = 0; i0 < nrec; i0 += 8 * WAVE) {
+            uint4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + u * WAVE + lane;
+                v[u] = i < nrec ? rec[i] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                b[0] = v[u].x > b[0] ? v[u].x : b[0];
+                b[1] = v[u].y > b[1] ? v[u].y : b[1];
+                b[2] = v[u].z > b[2] ? v[u].z : b[2];
+                b[3] = v[u].w > b[3] ? v[u].w : b[3];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = (uint32_t)wave_max_i32((int32_t)b[k]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) hdr->big_box[k] = b[k];
+        }
+    }
     // both loads in flight together (device-scope: written by other waves' atomics)
     unsigned long long key = load_relaxed(&hdr->key);
     const uint32_t flag = load_relaxed_u32(&hdr->serial_flag);
@@ -150,11 +200,6 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
         hdr->serial_flag = 0;
         hdr->nsat = 0;
         hdr->done = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            hdr->big_box[k] = load_relaxed_u32(&hdr->big_acc[k]);
-            hdr->big_acc[k] = 0;
-        }
     }
 }
 
@@ -171,13 +216,15 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
                                                  int64_t ntx, mshost::ScratchHeader *hdr,
                                                  const uint8_t *__restrict__ sat,
                                                  int32_t *__restrict__ bounds,
-                                                 int32_t *serial_state, ms_square *out) {
+                                                 const uint32_t *__restrict__ box_rec,
+                                                 int64_t nrec, int32_t *serial_state,
+                                                 ms_square *out) {
     const int lane = __lane_id();
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const uint32_t nsat = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->nsat));
     if (nsat == 0) {
-        if (wave == 0) finalize_wave(bits, m, n, ldw, hdr, serial_state, out);
+        if (wave == 0) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec);
         return;
     }
     // With few saturated tiles (a wide square: each one's height scan is long and there are
@@ -206,7 +253,7 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
     prev = (uint32_t)__shfl((int32_t)prev, 0);
     if (prev == (uint32_t)(nwave - 1)) {
         __threadfence();
-        finalize_wave(bits, m, n, ldw, hdr, serial_state, out);
+        finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec);
     }
 }
 
@@ -861,21 +908,25 @@ template <class TS>
 static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits, int64_t m,
                                       int64_t n, int64_t ldw, ScratchHeader *hdr,
                                       int32_t *serial_state, uint8_t *sat, int32_t *bounds,
-                                      ms_square *out) {
+                                      uint32_t *box_rec, ms_square *out) {
     const int64_t ntx = cdiv(cdiv(n, 64), TS::OWN_WORDS);
     const int64_t ntiles = cdiv(m, TS::TR) * ntx;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 4),
-                                                                   (int64_t)env.num_cus * 8));
+                                                                   max_probe_blocks(env.num_cus)));
+    if (!bounds) box_rec = nullptr;
     hipLaunchKernelGGL(msk::k_probe<TS>, dim3((unsigned)blocks), dim3(256), 0, env.stream, bits,
-                       m, n, ldw, ntiles, ntx, hdr, sat, bounds);
+                       m, n, ldw, ntiles, ntx, hdr, sat, bounds, box_rec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t rblocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 8),
                                                                     (int64_t)env.num_cus * 2));
     hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks), dim3(256), 0, env.stream,
-                       bits, m, n, ldw, ntiles, ntx, hdr, sat, bounds, serial_state, out);
+                       bits, m, n, ldw, ntiles, ntx, hdr, sat, bounds, box_rec, blocks,
+                       serial_state, out);
     return hipGetLastError();
 }
+
+int64_t max_probe_blocks(int num_cus) { return (int64_t)num_cus * 8; }
 
 int64_t max_probe_tiles(int64_t m, int64_t n) {
     const int64_t nw = cdiv(std::max<int64_t>(n, 1), 64);
@@ -885,11 +936,17 @@ int64_t max_probe_tiles(int64_t m, int64_t n) {
 
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, int32_t *bounds, ms_square *out) {
+                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out) {
     switch (variant) {
-    case 0: return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds, out);
-    case 1: return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds, out);
-    default: return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds, out);
+    case 0:
+        return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
+                                         box_rec, out);
+    case 1:
+        return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
+                                         box_rec, out);
+    default:
+        return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
+                                        box_rec, out);
     }
 }
 

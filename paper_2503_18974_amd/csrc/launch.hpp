@@ -20,12 +20,11 @@ struct ScratchHeader {
     uint32_t pad0;
     // Bounding box of the probe tiles whose largest side may exceed the narrow map's region
     // halo (bound above REGION_SMALL, or saturated), as {2^30 - first tile row, last tile row
-    // + 1, 2^30 - first tile column, last tile column + 1}, all zero when there is none:
-    // gathered by the probe with atomicMax, handed to the map (big_box) and cleared by the
-    // wave that writes the result.
-    uint32_t big_acc[4];
+    // + 1, 2^30 - first tile column, last tile column + 1}, all zero when there is none: each
+    // probe block stores the box of its tiles (BOX_RECORD_WORDS words), and the wave that
+    // writes the result folds those records into big_box for the map.
     uint32_t big_box[4];
-    uint64_t pad1[6];
+    uint64_t pad1[8];
 };
 static_assert(sizeof(ScratchHeader) == 128, "header layout");
 
@@ -48,11 +47,17 @@ struct LaunchEnv {
 hipError_t launch_pack_u8(const LaunchEnv &env, const uint8_t *a, int64_t m, int64_t n,
                           int64_t ldb, uint64_t *bits, int64_t ldw);
 
+// Per-block records of the probe's large-tile box: BOX_RECORD_WORDS uint32 per block (16-byte
+// aligned), for at most max_probe_blocks(num_cus) blocks.
+constexpr int BOX_RECORD_WORDS = 4;
+int64_t max_probe_blocks(int num_cus);
+
 // Largest square of one matrix; result into hdr->result and, if non-null, *out.  `sat` holds
-// one byte per probe tile (max_probe_tiles(m, n) bytes cover every variant).
+// one byte per probe tile (max_probe_tiles(m, n) bytes cover every variant); `bounds` one int32
+// per tile and `box_rec` the per-block box records, both filled for a map in the same call.
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, int32_t *bounds, ms_square *out);
+                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out);
 int64_t max_probe_tiles(int64_t m, int64_t n);
 
 // The map's narrow pass shortens its row bands (and narrows its window) until it has at least
