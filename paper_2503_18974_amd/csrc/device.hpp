@@ -749,18 +749,19 @@ __device__ __forceinline__ int64_t sat_run(const uint8_t *__restrict__ sat, int6
     }
 }
 
-// One pass over rows [ra, rb) of a tile with heights clamped at depth U and a window of U columns
-// to the left of the tile: *best / *bpos receive the rows' largest computed side and its first
-// cell.  A
+// One pass over rows [ra, rb) of the tiles in tile columns txa..txb (one tile row) with heights
+// clamped at depth U and a window of U columns to the left of them: *best / *bpos receive the
+// rows' largest computed side and its first cell.  A
 // true side s >= U still computes as >= U (clamping and clipping cannot push a value below U),
 // so a result below U is exact.  Returns false if the window exceeds one word per lane.
 template <class TS>
 __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
-                             int64_t ldw, int64_t ra, int64_t rb, int64_t tx, int64_t U,
-                             int32_t *best_out, int64_t *bpos_out) {
+                             int64_t ldw, int64_t ra, int64_t rb, int64_t txa, int64_t txb,
+                             int64_t U, int32_t *best_out, int64_t *bpos_out) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
-    const int64_t xa = tx * OWN_COLS, xb = xa + OWN_COLS < n ? xa + OWN_COLS : n;
+    const int64_t xa = txa * OWN_COLS;
+    const int64_t xb = (txb + 1) * OWN_COLS < n ? (txb + 1) * OWN_COLS : n;
     const int64_t nwords = (n + 63) >> 6;
     const int64_t w0 = xa - U > 0 ? ((xa - U) >> 6) : 0;
     const int64_t w1 = (xb + 63) >> 6;
@@ -892,7 +893,7 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
         U = U < ucap ? U : ucap;
         int32_t best = 0;
         int64_t bpos = 0;
-        if (!resolve_pass<TS>(bits, m, n, ldw, ra, rb, tx, U, &best, &bpos)) {
+        if (!resolve_pass<TS>(bits, m, n, ldw, ra, rb, tx, tx, U, &best, &bpos)) {
             // the serial pass finishes the matrix; serial_count counts the matrices so flagged
             if (lane == 0 && atomicOr(serial_flag, 1u) == 0u && serial_count)
                 atomicAdd(serial_count, 1u);
@@ -903,6 +904,73 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
             if (lane == 0 && best > 0) atomicMax(key, make_key(best, bpos));
             note_bound(bounds, ty * ntx + tx, best);
             return;
+        }
+        U = 2 * (int64_t)best;
+    }
+}
+
+// Saturated tiles of one tile row handled together: the tiles in columns tx0..tx1 (some of them
+// saturated) share one window and one height scan, and each row test covers all of them, so a
+// blob image whose tiles nearly all saturate needs fewer waves' worth of row tests (all the
+// groups then fit the device at once).  Each saturated tile's bound is computed as in resolve_tile; tiles that cannot reach the
+// best side so far keep that bound and drop out.  The span's largest side is exact for every
+// member (a member's true side is at most its bound, at most U once U reaches the span's bound)
+// and becomes each member's recorded bound.  Returns the members (bit k: column tx0 + k) still to
+// be resolved one at a time with resolve_tile: all of them where the span's window outgrows one
+// word per lane, or the single one left; 0 when the group is done.
+template <class TS>
+__device__ uint32_t resolve_group(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
+                                  int64_t ldw, int64_t ty, int64_t tx0, int64_t tx1,
+                                  int64_t ntx, const uint8_t *__restrict__ sat,
+                                  unsigned long long *key, int32_t *bounds) {
+    constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
+    const int lane = __lane_id();
+    m = uniform(m);
+    n = uniform(n);
+    ldw = uniform(ldw);
+    ty = uniform(ty);
+    tx0 = uniform(tx0);
+    tx1 = uniform(tx1);
+    const int64_t ta = ty * TS::TR, tb = ta + TS::TR < m ? ta + TS::TR : m;
+    const int64_t mn = m < n ? m : n;
+    const int64_t g = uniform(key_side(load_relaxed(key)));
+    // members still in the running (bit k), and the largest of their bounds
+    uint32_t live = 0;
+    int64_t lo = -1, hi = -1, ucap = 0;
+    for (int64_t tx = tx0; tx <= tx1; ++tx) {
+        if (!uniform((int32_t)sat[ty * ntx + tx])) continue;
+        const int64_t vrun = uniform(sat_run(sat, ty * ntx + tx, ntx, ty + 1, lane));
+        const int64_t hrun = uniform(sat_run(sat, ty * ntx + tx, 1, tx + 1, lane));
+        int64_t u = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
+        u = u < mn ? u : mn;
+        if (u < g) {  // cannot reach the best side found so far
+            note_bound(bounds, ty * ntx + tx, u);
+            continue;
+        }
+        live |= 1u << (tx - tx0);
+        if (lo < 0) lo = tx;
+        hi = tx;
+        ucap = u > ucap ? u : ucap;
+    }
+    if (__popc(live) <= 1) return live;
+    const auto fits = [&](int64_t U) {
+        const int64_t w0 = lo * OWN_COLS - U > 0 ? ((lo * OWN_COLS - U) >> 6) : 0;
+        const int64_t w1 = ((hi + 1) * OWN_COLS < n ? (hi + 1) * OWN_COLS + 63 : n + 63) >> 6;
+        return w1 - w0 <= WAVE && U + TS::TR + 1 < (1 << HB);
+    };
+    int64_t U = fits(ucap) ? ucap : 2 * (g > TS::KC ? g : TS::KC);
+    for (;;) {
+        U = U < ucap ? U : ucap;
+        int32_t best = 0;
+        int64_t bpos = 0;
+        if (!fits(U) || !resolve_pass<TS>(bits, m, n, ldw, ta, tb, lo, hi, U, &best, &bpos))
+            return live;
+        best = uniform(best);
+        if (best < U || U >= ucap) {
+            if (lane == 0 && best > 0) atomicMax(key, make_key(best, bpos));
+            for (uint32_t b = live; b; b &= b - 1)
+                note_bound(bounds, ty * ntx + tx0 + (__ffs(b) - 1), best);
+            return 0;
         }
         U = 2 * (int64_t)best;
     }

@@ -209,6 +209,11 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
 // writes it at once and every other wave returns.
 // Waves sharing one saturated tile in k_resolve (a divisor of the 4 waves of a block).
 constexpr int RESOLVE_PARTS = 4;
+// Neighbouring tile columns one wave resolves together when many tiles saturate (at most 32).
+// On a 16384^2 blob image (2804 of 3042 tiles saturated) the search takes 440 us one tile per
+// wave and 339 / 343 / 355 us with groups of 2 / 3 / 4: the gain is having every group in
+// flight at once, and smaller groups keep each tile's recorded bound tighter.
+constexpr int RESOLVE_GROUP = 2;
 
 template <class TS>
 __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bits, int64_t m,
@@ -233,9 +238,37 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
     // the scan of the rows above.  Groups of `parts` waves take tiles g, g + ngroups, ...: 64
     // saturation bytes per round.
     const int parts = (int64_t)nsat * RESOLVE_PARTS <= nwave ? RESOLVE_PARTS : 1;
+    if (parts == 1) {
+        // many saturated tiles: RESOLVE_GROUP neighbouring tile columns of a tile row per wave,
+        // sharing one window and one height scan (resolve_group)
+        const int64_t ngx = (ntx + RESOLVE_GROUP - 1) / RESOLVE_GROUP;
+        const int64_t ngroups = (ntiles / ntx) * ngx;
+        for (int64_t base = wave; base < ngroups; base += 64 * nwave) {
+            const int64_t gi = base + (int64_t)lane * nwave;
+            bool any = false;
+            if (gi < ngroups) {
+                const int64_t gy = gi / ngx, tx0 = (gi - gy * ngx) * RESOLVE_GROUP;
+                for (int k = 0; k < RESOLVE_GROUP && tx0 + k < ntx; ++k)
+                    any |= sat[gy * ntx + tx0 + k] != 0;
+            }
+            uint64_t b = __ballot(any);
+            while (b) {
+                const int l = __ffsll((long long)b) - 1;
+                b &= b - 1;
+                const int64_t gg = base + (int64_t)l * nwave;
+                const int64_t gy = gg / ngx, tx0 = (gg - gy * ngx) * RESOLVE_GROUP;
+                const int64_t tx1 = tx0 + RESOLVE_GROUP - 1 < ntx ? tx0 + RESOLVE_GROUP - 1 : ntx - 1;
+                uint32_t rest = resolve_group<TS>(bits, m, n, ldw, gy, tx0, tx1, ntx, sat,
+                                                  &hdr->key, bounds);
+                for (; rest; rest &= rest - 1)
+                    resolve_tile<TS>(bits, m, n, ldw, gy, tx0 + (__ffs(rest) - 1), ntx, sat,
+                                     &hdr->key, &hdr->serial_flag, bounds);
+            }
+        }
+    }
     const int64_t grp = wave / parts, ngrp = nwave / parts;
     const int part = (int)(wave % parts);
-    for (int64_t base = grp; base < ntiles; base += 64 * ngrp) {
+    for (int64_t base = grp; parts > 1 && base < ntiles; base += 64 * ngrp) {
         const int64_t t = base + (int64_t)lane * ngrp;
         uint64_t b = __ballot(t < ntiles && sat[t] != 0);
         while (b) {

@@ -106,6 +106,24 @@ def test_blob(dev):
     assert_same(a, dev)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("shape,sigma,pct,seed", [((1500, 4100), 9.0, 50.0, 21),
+                                                  ((2200, 2900), 12.0, 45.0, 22)])
+def test_blob_grouped_resolve(dev, variant, shape, sigma, pct, seed):
+    """Blob images where most tiles saturate: the resolve pass takes neighbouring tiles of a tile
+    row together (ragged tile columns, groups with unsaturated members), for every probe tile."""
+    announce("blob groups", variant, shape, seed)
+    a = W.gen_blob(shape[0], shape[1], sigma, pct, seed)
+    r0, c0 = shape[0] // 3, 2800  # a square across tile columns 2 and 3 (two groups)
+    a[r0:r0 + 120, c0:c0 + 120] = 1
+    ctx = M.Context()
+    try:
+        M.ms_set_config(ctx.handle, dict(probe_variant=variant, map_cols=4, map_band_rows=64))
+        assert_same(a, dev, ctx=ctx)
+    finally:
+        ctx.close()
+
+
 def test_every_candidate_identical(dev):
     """Every launch shape gives the same bits (a race or a missed barrier would differ)."""
     import torch
