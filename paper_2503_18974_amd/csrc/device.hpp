@@ -790,8 +790,7 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
             const int64_t r = r0 - u >= rstop ? r0 - u : rstop;  // clamped: the loads batch
             v[u] = bits[r * ldw + wl_c];
         }
-#pragma unroll
-        for (int u = 0; u < FB; ++u) {
+        for (int u = 0; u < FB; ++u) {  // stops at the scan's top: not unrolled
             if (r0 - u < rstop) break;
             acc &= v[u] & wmask;
             planes_inc_masked(P, acc);
@@ -1166,8 +1165,7 @@ __device__ void unit_rows_ge(const uint64_t *__restrict__ bits, int64_t m, int64
             const int64_t r = r0 - u >= rstop ? r0 - u : rstop;
             v[u] = bits[r * ldw + wl_c];
         }
-#pragma unroll
-        for (int u = 0; u < FB; ++u) {
+        for (int u = 0; u < FB; ++u) {  // stops at the scan's top: not unrolled
             if (r0 - u < rstop) break;
             acc &= v[u] & wmask;
             planes_inc_masked(P, acc);
