@@ -5,11 +5,13 @@
 //                its exact side (up to the side its halo certifies) with its first corner into
 //                one atomic key, and writes a saturation byte: 1 when it holds a larger square.
 //   k_resolve  : if any tile saturated, finishes those tiles exactly with column heights and a
-//                per-row test (device.hpp resolve_tile); the last wave to finish (or, with no
-//                saturated tile, the first wave) turns the key into the result (running the
-//                serial pass for a square too wide for the resolve pass) and clears the scratch.
+//                per-row test (device.hpp resolve_tile / resolve_group); the last wave to
+//                finish (or, with no saturated tile, the first wave) turns the key into the
+//                result (running the serial pass for a square too wide for the resolve pass)
+//                and clears the scratch.
 // dp map (one more launch): k_dpmap reads S on the device and covers the matrix with row bands
-// and column windows that start S rows / columns early (zero state there is exact).
+// and column windows that start S rows / columns early (zero state there is exact); after a
+// search in the same call, the halos follow each probe tile's bound.
 // Batched: k_batch_init (prefix of tile counts, clear keys), k_probe_batched (every tile of every
 // matrix in one grid-stride pass), k_batch_resolve (saturated tiles of every matrix),
 // k_batch_final (key -> result per matrix).
@@ -203,10 +205,11 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
     }
 }
 
-// After the probe: if any tile saturated, finish those tiles exactly (resolve_tile), spread over
-// the waves so that clustered saturated tiles land on different waves; the last wave to finish
-// (a completion count, no waiting) writes the result.  With no saturated tile, the first wave
-// writes it at once and every other wave returns.
+// After the probe: if any tile saturated, finish those tiles exactly (resolve_tile, or
+// resolve_group for neighbouring tiles), spread over the waves so that clustered saturated tiles
+// land on different waves; the last wave to finish (a completion count, no waiting) writes the
+// result.  With no saturated tile, the first wave writes it at once and every other wave returns.
+// The wave that writes the result also folds the probe blocks' large-tile box records.
 // Waves sharing one saturated tile in k_resolve (a divisor of the 4 waves of a block).
 constexpr int RESOLVE_PARTS = 4;
 // Neighbouring tile columns one wave resolves together when many tiles saturate (at most 32).
@@ -234,9 +237,9 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
     }
     // With few saturated tiles (a wide square: each one's height scan is long and there are
     // waves to spare) RESOLVE_PARTS waves share each tile, part = wave % parts taking a slice of
-    // its rows; with many (blob images) one wave takes a whole tile, since every part repeats
-    // the scan of the rows above.  Groups of `parts` waves take tiles g, g + ngroups, ...: 64
-    // saturation bytes per round.
+    // its rows, groups of `parts` waves taking tiles g, g + ngroups, ... (64 saturation bytes
+    // per round); with many (blob images) one wave takes whole tiles, RESOLVE_GROUP neighbours
+    // at a time, since every part would repeat the scan of the rows above.
     const int parts = (int64_t)nsat * RESOLVE_PARTS <= nwave ? RESOLVE_PARTS : 1;
     if (parts == 1) {
         // many saturated tiles: RESOLVE_GROUP neighbouring tile columns of a tile row per wave,
