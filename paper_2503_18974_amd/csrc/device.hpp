@@ -783,12 +783,24 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
     uint64_t acc = valid ? ~0ull : 0ull;
     const int64_t rstop = ra - U > 0 ? ra - U : 0;
     constexpr int FB = 16;  // rows loaded per round (all in flight together)
+    // the next round's rows are loaded while this round's are counted (a long scan, as above a
+    // large square, is otherwise one load latency per round)
+    uint64_t nv[FB];
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+        const int64_t r = ra - 1 - u >= rstop ? ra - 1 - u : rstop;  // clamped: the loads batch
+        nv[u] = rstop <= ra - 1 ? bits[r * ldw + wl_c] : 0ull;
+    }
     for (int64_t r0 = ra - 1; r0 >= rstop; r0 -= FB) {
         uint64_t v[FB];
 #pragma unroll
-        for (int u = 0; u < FB; ++u) {
-            const int64_t r = r0 - u >= rstop ? r0 - u : rstop;  // clamped: the loads batch
-            v[u] = bits[r * ldw + wl_c];
+        for (int u = 0; u < FB; ++u) v[u] = nv[u];
+        if (r0 - FB >= rstop) {
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int64_t r = r0 - FB - u >= rstop ? r0 - FB - u : rstop;
+                nv[u] = bits[r * ldw + wl_c];
+            }
         }
         for (int u = 0; u < FB; ++u) {  // stops at the scan's top: not unrolled
             if (r0 - u < rstop) break;
