@@ -208,7 +208,7 @@ ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M,
                       int64_t ld_words, ms_cube *d_out, void *d_workspace,
                       size_t workspace_bytes, void *stream);
 
-/* Autotuning.  ms_num_candidates / ms_candidate enumerate the launch shapes this build can
+/* Autotuning.  ms_num_candidates / ms_candidate enumerate the launch shapes the library can
  * run; ms_set_config forces one (NULL restores tuned/default choices); ms_get_config reports
  * the shape that would be used for an m x n matrix.  ms_autotune times every candidate on the
  * caller's packed matrix (blocking: it synchronises `stream`) and records the fastest for
