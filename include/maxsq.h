@@ -101,7 +101,10 @@ ms_status ms_pack_u8(ms_ctx *ctx, const uint8_t *d_a, int64_t m, int64_t n, int6
  * paper's Algorithm 1 computes, as the side rather than the area).  Writes one ms_square to
  * d_out (device or pinned host memory).
  * Invalid: m or n < 0; d_bits NULL with m * n > 0; d_out NULL; ld_words < ceil(n/64);
- * m * n >= 2^44.
+ * m * n >= 2^44.  MS_ERR_UNSUPPORTED when min(m, n) >= 2^20: the side and the corner travel
+ * through the device as one 64-bit key (20 bits of side, 44 of position), so sides must stay
+ * below 2^20.  The same limits apply to every call below that takes a packed matrix (each
+ * descriptor of a batch included).
  */
 ms_status ms_max_square(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                         int64_t ld_words, ms_square *d_out, void *stream);

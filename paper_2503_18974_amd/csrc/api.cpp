@@ -17,6 +17,9 @@
 namespace {
 
 constexpr int64_t POS_LIMIT = int64_t(1) << 44;  // cells addressable by the result key
+// Sides the result key holds: 64 - 44 = 20 bits.  A side is at most min(m, n), so matrices with
+// min(m, n) below this limit always fit.
+constexpr int64_t SIDE_LIMIT = int64_t(1) << 20;
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -238,6 +241,7 @@ ms_status validate_packed(const uint64_t *bits, int64_t m, int64_t n, int64_t ld
     if (ldw < cdiv(n, 64)) return MS_ERR_INVALID_ARGUMENT;
     if (mul_overflows(m, n) || m * n >= POS_LIMIT) return MS_ERR_INVALID_ARGUMENT;
     if (mul_overflows(m, ldw)) return MS_ERR_INVALID_ARGUMENT;
+    if (std::min(m, n) >= SIDE_LIMIT) return MS_ERR_UNSUPPORTED;
     return MS_OK;
 }
 

@@ -199,3 +199,24 @@ def test_max_cube_workspace_checked():
     assert M.lib().ms_max_cube_workspace_size(None, 3, 4, 130, C.byref(n)) == 0
     assert n.value >= 3 * 3 * 4 * 3 * 8
     assert M.lib().ms_max_cube(None, P, 3, 4, 130, 3, P, P, n.value - 1, None) == 2
+
+
+def test_side_beyond_key_field_is_unsupported():
+    """The result key holds sides below 2^20, so a matrix whose shorter dimension reaches 2^20
+    (e.g. an all-ones 2^20 x 2^20 matrix, 128 GiB packed) is refused before any device work
+    instead of coming back with a truncated side; one row or column less is accepted by the
+    host checks."""
+    L = M.lib()
+    unsupported = 5
+    big = 1 << 20
+    assert L.ms_max_square(None, P, big, big, big // 64, P, None) == unsupported
+    assert L.ms_square_map(None, P, big, big, big // 64, P, big, P, None) == unsupported
+    assert L.ms_square_map_from_max(None, P, big, big, big // 64, P, P, big, None) == unsupported
+    assert L.ms_all_max_squares(None, P, big, big, big // 64, P, P, 4, P, P, 1 << 40,
+                                None) == unsupported
+    size = ctypes.c_size_t()
+    mats = (M._Matrix * 2)(M._Matrix(P, 4, 4, 1), M._Matrix(P, big, big, big // 64))
+    assert L.ms_batched_workspace_size(None, mats, 2, ctypes.byref(size)) == unsupported
+    assert L.ms_max_square_batched(None, mats, P, 2, P, P, 1 << 40, None) == unsupported
+    mats[1] = M._Matrix(P, big - 1, big, big // 64)
+    assert L.ms_batched_workspace_size(None, mats, 2, ctypes.byref(size)) == 0
