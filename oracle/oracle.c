@@ -18,8 +18,8 @@
  * that keeps only the previous row (O(n) memory), used for very large matrices and for
  * streaming rows out chunk by chunk.
  *
- * Also here, as a second witness: the paper's frequency-based Algorithm 1 as written
- * (Section 3), with a record of where found_max_width is incremented.
+ * Also here, as a second witness: the paper's frequency-based method (Section 3), written
+ * from its description, with a record of where the best side was last raised.
  *
  * And the largest all-ones rectangle (the extension of Section 6's future work, in the
  * histogram form of Section 2.3), by its plain definition; see max_rect below.  And the largest
@@ -249,14 +249,19 @@ int oracle_unpack(const uint64_t *bits, int64_t m, int64_t n, int64_t ld_words, 
 }
 
 /*
- * ---- second witness: Algorithm 1 (frequency-based MaximalSquare), Section 3 ----
- * freq[j] counts consecutive ones ending at the current row in column j; a single
- * threshold k (the paper's check_max_width and check_max_height, which always move
- * together) is the side being looked for; counter is the run of consecutive columns whose
- * freq reaches k; when it equals k a square of side k has been found, found_max_width,
- * the threshold and the counter move as the paper prescribes.  Additions for testing only:
- * res = {found, row, col} where (row, col) is the cell at the last increment, and
- * row_trace[i] (nullable) = found after row i.  Returns the side, not the area.
+ * ---- second witness: the frequency-based method of Section 3 ----
+ * Written from the method's description, in this file's own structure.  h[j] is the
+ * frequency array: the number of consecutive ones ending at the current row in column j.
+ * `best` is the largest side confirmed so far, and the only side worth looking for in the
+ * next row is k = best + 1 (the method's dynamic threshold): a square of side k ending in
+ * row i needs k consecutive columns whose heights all reach k.  Each row is handled in two
+ * sweeps: the heights of the whole row are brought up to date first, then the row is walked
+ * once, counting the run of consecutive columns with h >= k; the first column where that
+ * run reaches k confirms side k there.  No second confirmation can happen in the same row,
+ * since a side can grow by at most one per row (dp[i][j] <= dp[i-1][j-1] + 1), so the walk
+ * stops at the first one.  Test additions: res = {best, row, col} with (row, col) the cell
+ * where best was last raised, and row_trace[i] (nullable) = best after row i.  Returns the
+ * side, not the area.
  */
 int oracle_freq_alg1_u8(const uint8_t *a, int64_t m, int64_t n, int64_t ld, int64_t res[3],
                         int64_t *row_trace) {
@@ -266,36 +271,26 @@ int oracle_freq_alg1_u8(const uint8_t *a, int64_t m, int64_t n, int64_t ld, int6
     int e = check_dims(m, n, ld, n, a);
     if (e) return e;
     if (m == 0 || n == 0) return ORACLE_OK;
-    int64_t *freq = (int64_t *)calloc((size_t)n, sizeof(int64_t));
-    if (!freq) return ORACLE_ENOMEM;
-    int64_t found = 0, check_w = 1, check_h = 1, counter = 0;
+    int64_t *h = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!h) return ORACLE_ENOMEM;
+    int64_t best = 0;
     for (int64_t i = 0; i < m; ++i) {
-        counter = 0;
+        for (int64_t j = 0; j < n; ++j) h[j] = cell_u8(a, ld, i, j) ? h[j] + 1 : 0;
+        const int64_t k = best + 1;
+        int64_t run = 0;
         for (int64_t j = 0; j < n; ++j) {
-            if (!cell_u8(a, ld, i, j)) {
-                freq[j] = 0;
-                counter = 0;
-                continue;
-            }
-            freq[j] += 1;
-            if (freq[j] < check_h) {
-                counter = 0;
-                continue;
-            }
-            counter += 1;
-            if (counter == check_w) {
-                found += 1;
-                check_w += 1;
-                check_h += 1;
-                counter = 0;
+            run = h[j] >= k ? run + 1 : 0;
+            if (run == k) {
+                best = k;
                 res[1] = i;
                 res[2] = j;
+                break;
             }
         }
-        if (row_trace) row_trace[i] = found;
+        if (row_trace) row_trace[i] = best;
     }
-    res[0] = found;
-    free(freq);
+    res[0] = best;
+    free(h);
     return ORACLE_OK;
 }
 
