@@ -85,81 +85,51 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(mats, budget_s):
-    """The oracle as it stands (plain C dp, full table) on a bounded sample of the workload."""
-    import oracle
-    done_cells, t_total, names = 0, 0.0, []
-    for (n, d, p, seed), a in mats:
-        t0 = time.perf_counter()
-        oracle.square_map(a)
-        t_total += time.perf_counter() - t0
-        done_cells += a.size
-        names.append("%dx%d p=%.1f" % (n, n, p))
-        if t_total > budget_s:
-            break
-    return {"value": done_cells / t_total / 1e9, "unit": "Gcells/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of the 45 grid matrices (%s ...), %.0f Mcells, one full-table dp pass "
-                      "each, %.1f s" % (len(names), ", ".join(names[:3]), done_cells / 1e6, t_total)}
+def cpu_timing(threads=0, sample="grid15"):
+    """The CPU baselines, timed by oracle/cpu_timing.py in a child process: oracle.c built
+    -O3 -march=native for this host, 3 warm-ups, 5-50 timed runs per matrix, 10 %-trimmed
+    mean.  One pinned core (taskset -c, the last core this process may use) unless `threads`,
+    then one pinned pool thread per core."""
+    import subprocess
+    cores = sorted(os.sched_getaffinity(0))
+    cmd = [sys.executable, "-m", "oracle.cpu_timing", "--sample", sample]
+    if threads:
+        cmd += ["--threads", str(threads)]
+    else:
+        cmd = ["taskset", "-c", str(cores[-1])] + cmd
+    out = subprocess.run(cmd, cwd=ROOT, check=True, capture_output=True, text=True).stdout
+    rec = json.loads(out.strip().splitlines()[-1])
+    rec["pinning"] = ("taskset -c %d" % cores[-1]) if not threads else \
+        "one pool thread per core, each pinned with sched_setaffinity"
+    return rec
 
 
-def cpu_freq_baseline(mats, budget_s):
-    """The paper's Algorithm 1 (plain C, largest side only) next to the oracle's rolling-row dp
-    on the same matrices: the host's DP/frequency ratio, for context."""
-    import oracle
-    t_f = t_d = 0.0
-    done = 0
-    for (n, d, p, seed), a in mats:
-        t0 = time.perf_counter()
-        oracle.freq_alg1(a)
-        t1 = time.perf_counter()
-        oracle.max_square(a)
-        t2 = time.perf_counter()
-        t_f += t1 - t0
-        t_d += t2 - t1
-        done += 1
-        if t_f + t_d > budget_s:
-            break
-    cells = sum(a.size for _, a in mats[:done])
-    return {"freq_alg1_gcells_s": cells / t_f / 1e9, "dp_rolling_gcells_s": cells / t_d / 1e9,
-            "dp_over_freq_time": t_d / t_f, "cores": 1,
-            "sample": "%d grid matrices, %.0f Mcells, largest side only" % (done, cells / 1e6)}
-
-
-def host_cpu():
-    """(model name, cores this process may use) of the host."""
-    model = "unknown"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return model, len(os.sched_getaffinity(0))
-
-
-def cpu_all_cores_baseline(mats, budget_s):
-    """The paper's Algorithm 1 and the oracle's rolling-row dp over the grid matrices with one
-    host thread per core (the C calls release the GIL), matrices dealt to a thread pool: the
-    multi-core CPU figure the paper leaves to future work."""
-    from concurrent.futures import ThreadPoolExecutor
-    import oracle
-    model, cores = host_cpu()
-    out = {"cores": cores, "cpu": model}
-    # the grid, largest matrices first, repeated until about budget_s / 2 per kind has passed
-    order = sorted((a for _, a in mats), key=lambda a: -a.size)
-    for kind, fn in (("freq_alg1", oracle.freq_alg1), ("dp_rolling", oracle.max_square)):
-        done_cells, passes, t0 = 0, 0, time.perf_counter()
-        with ThreadPoolExecutor(cores) as ex:
-            while passes == 0 or time.perf_counter() - t0 < budget_s / 2:
-                list(ex.map(fn, order))
-                done_cells += sum(a.size for a in order)
-                passes += 1
-        t = time.perf_counter() - t0
-        out[kind + "_gcells_s"] = done_cells / t / 1e9
-        out[kind + "_sample"] = "%d passes over the %d grid matrices, %.0f Mcells, %.1f s" % (
-            passes, len(order), done_cells / 1e6, t)
-    return out
+def cpu_sections():
+    """cpu_baseline (the oracle, one core), cpu_freq_alg1 (the frequency method of Section 3
+    against the O(n)-space DP, one core) and cpu_all_cores (both over every allowed core)."""
+    one = cpu_timing()
+    proto = ("%s; %d warm-ups, 5-50 timed runs per matrix (fewer for larger ones), mean after "
+             "dropping the fastest and slowest %d %%; %s" % (one["compiler"], one["warmup"],
+                                                            int(100 * one["trim_each_side"]),
+                                                            one["pinning"]))
+    sample = ("%d grid matrices (p in {0.1, 0.5, 0.9} at every side 1000..5000), %.0f Mcells "
+              "per pass" % (one["matrices"], one["dp_full"]["cells"] / 1e6))
+    base = {"value": one["dp_full"]["gcells_s"], "unit": "Gcells/s", "cores": 1, "kind": "oracle",
+            "sample": sample + "; the oracle's full-table dp (Section 2.1 eq. (1))",
+            "protocol": proto, "cpu": one["cpu"],
+            "per_matrix": one["dp_full"]["per_matrix"]}
+    freq = {"freq_alg1_gcells_s": one["freq"]["gcells_s"],
+            "dp_rolling_gcells_s": one["dp_rolling"]["gcells_s"],
+            "dp_over_freq_time": one["freq"]["gcells_s"] / one["dp_rolling"]["gcells_s"],
+            "cores": 1, "cpu": one["cpu"], "protocol": proto, "sample": sample}
+    allc = cpu_timing(threads=len(os.sched_getaffinity(0)))
+    every = {"cores": allc["threads"], "cpu": allc["cpu"], "compiler": allc["compiler"],
+             "freq_alg1_gcells_s": allc["freq"]["gcells_s"],
+             "dp_rolling_gcells_s": allc["dp_rolling"]["gcells_s"],
+             "dp_full_gcells_s": allc["dp_full"]["gcells_s"],
+             "sample": sample + "; matrices dealt over a pool of pinned threads, "
+                       "same warm-up and run counts per matrix, cells over wall time"}
+    return base, freq, every
 
 
 def large_section(L, h, dev, names, reps, golden):
@@ -595,7 +565,6 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -907,13 +876,12 @@ def main():
         extra["multi_stream_step"] = multi
     out.update(extra)
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)
-        out["cpu_baseline"] = cpu_baseline(mats, args.cpu_budget)
-        out["cpu_freq_alg1"] = cpu_freq_baseline(mats, args.cpu_budget)
-        out["cpu_freq_alg1"]["cpu"] = host_cpu()[0]
-        out["cpu_all_cores"] = cpu_all_cores_baseline(mats, args.cpu_budget)
-        log("CPU, all %d cores: Algorithm 1 %.2f Gcells/s, rolling-row dp %.2f Gcells/s"
-            % (out["cpu_all_cores"]["cores"], out["cpu_all_cores"]["freq_alg1_gcells_s"],
+        log("timing the CPU baselines (oracle.c -O3 -march=native, pinned)")
+        out["cpu_baseline"], out["cpu_freq_alg1"], out["cpu_all_cores"] = cpu_sections()
+        log("CPU, one core: oracle dp %.3f Gcells/s, frequency method %.3f Gcells/s; all %d "
+            "cores: frequency method %.2f Gcells/s, rolling-row dp %.2f Gcells/s"
+            % (out["cpu_baseline"]["value"], out["cpu_freq_alg1"]["freq_alg1_gcells_s"],
+               out["cpu_all_cores"]["cores"], out["cpu_all_cores"]["freq_alg1_gcells_s"],
                out["cpu_all_cores"]["dp_rolling_gcells_s"]))
     ctx.close()
     print(json.dumps(out), flush=True)
