@@ -15,6 +15,13 @@ arrive on their own schedule.  The loop:
   * polls the slots' completion events, hands each result to the caller, and frees the
     request's memory.
 
+Failures stay with the requests they concern: a request that is malformed or larger than the
+whole budget is rejected at admission; a batch whose launch or result collection fails fails
+only its own requests (their memory is freed and the loop goes on); a device error seen while
+polling (the stream can no longer report) fails every request in flight and every request not
+yet served, and ends the run.  A request can be cancelled at any time: before launch it is
+dropped, in flight its result is discarded when the batch completes.
+
 Latency is measured from a request's arrival time to the moment the loop sees its result;
 p50/p99 come from those.  The executor is an interface so the scheduling logic is tested on
 the CPU with a simulated device (tests/test_serve.py); GpuExecutor drives the library.
@@ -53,6 +60,22 @@ class Request:
     done: float | None = None
     result: tuple | None = None
     error: str | None = None
+    cancelled: bool = False
+
+    def cancel(self) -> None:
+        """Ask the server to drop this request (before launch) or discard its result."""
+        self.cancelled = True
+
+    def invalid(self) -> str | None:
+        """Why the request cannot be served, or None."""
+        if int(self.m) < 0 or int(self.n) < 0:
+            return "negative dimensions"
+        shape = getattr(self.bits, "shape", None)
+        if self.cells and shape is not None:
+            if len(shape) != 2 or int(shape[0]) != int(self.m) or int(shape[1]) < self.ld_words:
+                return "packed bits of shape %s do not hold %d rows of %d words" % (
+                    tuple(shape), int(self.m), self.ld_words)
+        return None
 
     @property
     def cells(self) -> int:
@@ -149,6 +172,8 @@ class Stats:
     requests: int = 0
     completed: int = 0
     rejected: int = 0
+    failed: int = 0
+    cancelled: int = 0
     batches: int = 0
     cells: int = 0
     max_queue: int = 0
@@ -172,6 +197,7 @@ class Stats:
             "p99_queue_ms": p99(self.queue_waits), "p99_launch_wait_ms": p99(self.launch_waits),
             "p99_device_ms": p99(self.device_times),
             "requests": self.requests, "completed": self.completed, "rejected": self.rejected,
+            "failed": self.failed, "cancelled": self.cancelled,
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3),
@@ -216,6 +242,19 @@ class Server:
         inflight = []       # [(handle, [(req, bits_off, map_off)])]
         nxt = 0
         clk = self.clock
+
+        def release_memory(items):
+            for _, boff, moff in items:
+                self.arena.free(boff)
+                if moff is not None:
+                    self.arena.free(moff)
+
+        def fail(items, why):
+            for r, _, _ in items:
+                r.error = why
+                st.failed += 1
+            release_memory(items)
+
         while nxt < len(reqs) or queue or pending or inflight:
             now = clk.now()
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
@@ -224,35 +263,68 @@ class Server:
             st.max_queue = max(st.max_queue, len(queue))
             # completions, in any order
             still = []
-            for h, items in inflight:
-                if self.ex.done(h):
-                    res = self.ex.finish(h)
-                    t = clk.now()
-                    for (r, boff, moff), rv in zip(items, res):
-                        r.done = t
-                        r.result = tuple(int(v) for v in rv)
-                        if self.on_complete:
-                            self.on_complete(r, self.ex.map_view(h, r, moff))
-                        self.arena.free(boff)
-                        if moff is not None:
-                            self.arena.free(moff)
-                        st.completed += 1
-                        st.cells += r.cells
-                        st.latencies.append(r.done - r.arrival)
-                        st.queue_waits.append(r.admitted - r.arrival)
-                        st.launch_waits.append(r.launched - r.admitted)
-                        st.device_times.append(r.done - r.launched)
-                        st.last_done = max(st.last_done, t)
-                    self.ex.release(h)
-                else:
+            device_error = None
+            for k, (h, items) in enumerate(inflight):
+                try:
+                    finished = self.ex.done(h)
+                except Exception as e:  # the device can no longer report: see below
+                    device_error = "device error: %s" % e
+                    still.extend(inflight[k:])
+                    break
+                if not finished:
                     still.append((h, items))
+                    continue
+                try:
+                    res = self.ex.finish(h)
+                except Exception as e:  # this batch's results are unusable
+                    fail(items, "batch failed: %s" % e)
+                    self.ex.release(h)
+                    continue
+                t = clk.now()
+                for (r, boff, moff), rv in zip(items, res):
+                    if r.cancelled:
+                        r.error = "cancelled"
+                        st.cancelled += 1
+                        continue
+                    r.done = t
+                    r.result = tuple(int(v) for v in rv)
+                    if self.on_complete:
+                        self.on_complete(r, self.ex.map_view(h, r, moff))
+                    st.completed += 1
+                    st.cells += r.cells
+                    st.latencies.append(r.done - r.arrival)
+                    st.queue_waits.append(r.admitted - r.arrival)
+                    st.launch_waits.append(r.launched - r.admitted)
+                    st.device_times.append(r.done - r.launched)
+                    st.last_done = max(st.last_done, t)
+                release_memory(items)
+                self.ex.release(h)
+            if device_error is not None:
+                # every request not yet served fails with the error, and nothing more is
+                # launched: the batches still in flight, the admitted ones, the queue and the
+                # arrivals to come
+                for _, items in still:
+                    fail(items, device_error)
+                fail(pending, device_error)
+                for r in list(queue) + reqs[nxt:]:
+                    r.error = device_error
+                    st.failed += 1
+                return st
             inflight = still
             # admission: arrival order, while the budget holds the next request
             while queue and len(pending) < self.max_batch:
                 r = queue[0]
-                if r.device_bytes > self.arena.capacity:
+                if r.cancelled:
                     queue.popleft()
-                    r.error = "larger than the HBM budget"
+                    r.error = "cancelled"
+                    st.cancelled += 1
+                    continue
+                why = r.invalid()
+                if why is None and r.device_bytes > self.arena.capacity:
+                    why = "larger than the HBM budget"
+                if why is not None:
+                    queue.popleft()
+                    r.error = why
                     st.rejected += 1
                     continue
                 boff = self.arena.alloc(r.bits_bytes)
@@ -268,12 +340,25 @@ class Server:
                 r.admitted = clk.now()
                 pending.append((r, boff, moff))
             st.peak_bytes = max(st.peak_bytes, self.arena.in_use)
+            # requests cancelled while admitted are dropped before launch
+            if any(r.cancelled for r, _, _ in pending):
+                gone = [x for x in pending if x[0].cancelled]
+                pending = [x for x in pending if not x[0].cancelled]
+                for r, _, _ in gone:
+                    r.error = "cancelled"
+                    st.cancelled += 1
+                release_memory(gone)
             # launch everything admitted on a free slot
             if pending and len(inflight) < self.slots:
                 t = clk.now()
                 for r, _, _ in pending:
                     r.launched = t
-                h = self.ex.launch(pending)
+                try:
+                    h = self.ex.launch(pending)
+                except Exception as e:  # only this batch fails; its memory returns
+                    fail(pending, "launch failed: %s" % e)
+                    pending = []
+                    continue
                 inflight.append((h, pending))
                 st.batches += 1
                 st.batch_sizes.append(len(pending))
@@ -338,11 +423,22 @@ class GpuExecutor:
         return t.pin_memory()
 
     def launch(self, batch):
-        torch = self.torch
+        """Enqueue a batch on a free slot.  On failure the slot's stream is drained (so no copy
+        into the batch's arena memory is still pending when the server frees it), the slot is
+        freed, and the error is raised for the server to fail this batch alone."""
         slot = next(s for s in self.slots if not s["busy"])
         slot["busy"] = True
-        if len(batch) > self.max_batch:
-            raise ValueError("batch larger than the executor's max_batch")
+        try:
+            if len(batch) > self.max_batch:
+                raise ValueError("batch larger than the executor's max_batch")
+            return self._enqueue(slot, batch)
+        except Exception:
+            slot["stream"].synchronize()
+            slot["busy"] = False
+            raise
+
+    def _enqueue(self, slot, batch):
+        torch = self.torch
         st = slot["stream"]
         sp = st.cuda_stream
         h = slot["h_mats"]

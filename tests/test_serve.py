@@ -233,3 +233,166 @@ def test_request_pool_recipe():
     kinds = [W.serving_request(k, hi=128)[3] for k in range(200)]
     frac = kinds.count("bernoulli") / len(kinds)
     assert 0.6 < frac < 0.8
+
+
+# ------------------------------------------------------------------------------ failures
+
+class FlakyExecutor(FakeExecutor):
+    """FakeExecutor whose k-th launch raises (launch_fail), whose result collection of the k-th
+    batch raises (finish_fail), or whose completion poll raises from time t on (dead_at)."""
+
+    def __init__(self, clock, arena_ref, launch_fail=(), finish_fail=(), dead_at=None, **kw):
+        super().__init__(clock, arena_ref, **kw)
+        self.launch_fail = set(launch_fail)
+        self.finish_fail = set(finish_fail)
+        self.dead_at = dead_at
+        self.n_launch = 0
+
+    def launch(self, batch):
+        k = self.n_launch
+        self.n_launch += 1
+        if k in self.launch_fail:
+            raise RuntimeError("injected launch failure")
+        h = super().launch(batch)
+        h["k"] = k
+        return h
+
+    def done(self, h):
+        if self.dead_at is not None and self.clock.now() >= self.dead_at:
+            raise RuntimeError("injected device error")
+        return super().done(h)
+
+    def finish(self, h):
+        if h["k"] in self.finish_fail:
+            raise RuntimeError("injected result failure")
+        return super().finish(h)
+
+
+def flaky_server(budget, slots=2, max_batch=8, base=1e-4, **kw):
+    clk = VirtualClock()
+    holder = {}
+    ex = FlakyExecutor(clk, lambda: holder["s"].arena, base=base, **kw)
+    s = Server(ex, budget, slots=slots, max_batch=max_batch, clock=clk)
+    holder["s"] = s
+    return s, ex
+
+
+def launched_batches(ex):
+    return [rids for _, rids, _ in ex.launches]
+
+
+def test_launch_failure_fails_only_that_batch():
+    """An executor failure mid-run (the third launch raises): that batch's requests fail with
+    the error, every other request completes with the oracle's result, no memory leaks."""
+    pool = small_pool(6, seed=11)
+    reqs = make_requests(pool, 80, rate=20000.0, map_fraction=0.3)
+    s, ex = flaky_server(1 << 24, launch_fail={2})
+    st = s.run(reqs)
+    failed = [r for r in reqs if r.error]
+    assert failed and all("injected launch failure" in r.error for r in failed)
+    assert all(r.result is None for r in failed)
+    assert st.failed == len(failed) and st.completed == 80 - len(failed)
+    for r in reqs:
+        if not r.error:
+            assert r.result == oracle.max_square_packed(np.asarray(r.bits), r.n)
+    assert s.arena.in_use == 0 and ex.live_slots == 0
+
+
+def test_result_failure_fails_only_that_batch():
+    pool = small_pool(6, seed=12)
+    reqs = make_requests(pool, 60, rate=20000.0, map_fraction=0.2)
+    s, ex = flaky_server(1 << 24, finish_fail={1, 3})
+    st = s.run(reqs)
+    bad = set(launched_batches(ex)[1]) | set(launched_batches(ex)[3])
+    for r in reqs:
+        if r.rid in bad:
+            assert r.error and "injected result failure" in r.error and r.result is None
+        else:
+            assert r.error is None and r.result == oracle.max_square_packed(np.asarray(r.bits),
+                                                                             r.n)
+    assert st.failed == len(bad) and st.completed == 60 - len(bad)
+    assert s.arena.in_use == 0 and ex.live_slots == 0
+
+
+def test_device_error_reaches_every_unserved_request():
+    """A device error while polling: every request in flight, admitted, queued or still to
+    arrive fails with it, the ones already served keep their results, and the run ends."""
+    pool = small_pool(6, seed=13)
+    reqs = make_requests(pool, 100, rate=10000.0, map_fraction=0.0)
+    t_dead = sorted(r.arrival for r in reqs)[40]
+    s, ex = flaky_server(1 << 24, slots=2, base=5e-4, dead_at=t_dead)
+    st = s.run(reqs)
+    served = [r for r in reqs if r.result is not None]
+    lost = [r for r in reqs if r.result is None]
+    assert served and lost
+    assert all(r.error and "injected device error" in r.error for r in lost)
+    assert all(r.done is not None and r.done < t_dead + 1e-12 for r in served)
+    assert st.completed == len(served) and st.failed == len(lost)
+    assert s.arena.in_use == 0
+
+
+def test_cancellation_before_and_during_flight():
+    """Requests cancelled before arrival are never launched; a request cancelled after its
+    launch (by the executor, standing in for a client) has its result discarded; the others
+    are untouched."""
+    pool = small_pool(6, seed=14)
+    reqs = make_requests(pool, 60, rate=20000.0, map_fraction=0.3)
+    early = {5, 17, 33}
+    for r in reqs:
+        if r.rid in early:
+            r.cancel()
+    s, ex = flaky_server(1 << 24)
+    late = {}
+    orig_launch = ex.launch
+
+    def launch_and_cancel(batch):
+        h = orig_launch(batch)
+        if len(late) < 2:
+            r = batch[-1][0]
+            late[r.rid] = r
+            r.cancel()
+        return h
+
+    ex.launch = launch_and_cancel
+    st = s.run(reqs)
+    launched = {rid for rids in launched_batches(ex) for rid in rids}
+    assert not (early & launched)
+    for r in reqs:
+        if r.rid in early or r.rid in late:
+            assert r.error == "cancelled" and r.result is None
+        else:
+            assert r.result == oracle.max_square_packed(np.asarray(r.bits), r.n)
+    assert set(late) <= launched
+    assert st.cancelled == len(early) + len(late)
+    assert st.completed == 60 - st.cancelled
+    assert s.arena.in_use == 0
+
+
+def test_invalid_requests_are_rejected_with_a_reason():
+    pool = small_pool(4, seed=15)
+    reqs = make_requests(pool, 20, rate=5000.0, map_fraction=0.0)
+    good_bits = W.gen_bernoulli_packed(40, 100, 0.5, 3)
+    reqs.append(Request(rid=100, m=-3, n=10, bits=good_bits, arrival=0.0005))
+    reqs.append(Request(rid=101, m=50, n=100, bits=good_bits, arrival=0.0007))   # 40 rows given
+    reqs.append(Request(rid=102, m=40, n=200, bits=good_bits, arrival=0.0009))   # 2 words < 4
+    s, ex, clk = make_server(budget=1 << 22)
+    st = s.run(reqs)
+    bad = [r for r in reqs if r.rid >= 100]
+    assert all(r.error and r.result is None for r in bad)
+    assert st.rejected == 3 and st.completed == 20
+    launched = {rid for _, rids, _ in ex.launches for rid in rids}
+    assert not ({100, 101, 102} & launched)
+
+
+def test_arrival_burst_is_served_in_order():
+    """Every request arrives at the same instant: all are served, admission stays first come,
+    first served, and batches never exceed max_batch."""
+    pool = small_pool(5, seed=16)
+    reqs = [Request(rid=k, m=m, n=n, bits=b, arrival=0.001)
+            for k, (b, m, n) in enumerate(pool * 30)]
+    s, ex, clk = make_server(budget=1 << 22, slots=2, max_batch=16)
+    st = s.run(reqs)
+    assert st.completed == len(reqs)
+    assert max(st.batch_sizes) <= 16
+    order = [rid for _, rids, _ in ex.launches for rid in rids]
+    assert order == sorted(order)
