@@ -21,7 +21,9 @@ constexpr int64_t POS_LIMIT = int64_t(1) << 44;  // cells addressable by the res
 // min(m, n) below this limit always fit.
 constexpr int64_t SIDE_LIMIT = int64_t(1) << 20;
 
-int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// ceil(a / b) for a >= 0, b > 0, without forming a + b - 1 (a may be near INT64_MAX when an
+// argument is being validated)
+int64_t cdiv(int64_t a, int64_t b) { return a / b + (a % b != 0); }
 
 bool mul_overflows(int64_t a, int64_t b) {
     return a > 0 && b > 0 && a > INT64_MAX / b;
@@ -272,7 +274,10 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
 extern "C" {
 
 const char *ms_status_string(ms_status s) {
-    switch (s) {
+    // a C caller may pass any int: read it as one, not as the enum (whose range is 0..7 in C++)
+    int v = 0;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
     case MS_OK: return "ok";
     case MS_ERR_INVALID_ARGUMENT: return "invalid argument";
     case MS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
