@@ -33,8 +33,8 @@
  * returned without touching the device.  A failed launch or allocation returns MS_ERR_HIP or
  * MS_ERR_OUT_OF_MEMORY.  No call aborts or throws across the ABI.
  *
- * Context: `ctx` may be NULL in every call below; the library then uses a default context
- * for the current HIP device, created on first use.
+ * Context: `ctx` may be NULL in every call below except ms_max_square_noalloc; the library
+ * then uses a default context for the current HIP device, created on first use.
  */
 #ifndef MAXSQ_H
 #define MAXSQ_H
@@ -108,6 +108,26 @@ ms_status ms_pack_u8(ms_ctx *ctx, const uint8_t *d_a, int64_t m, int64_t n, int6
  */
 ms_status ms_max_square(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                         int64_t ld_words, ms_square *d_out, void *stream);
+
+/*
+ * ms_max_square for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same search and the same result, but the call
+ * allocates nothing, neither device nor host memory.  Its scratch is one fixed array of the
+ * library per GPU (4 MiB + 256 bytes), held from the library's load until the process ends;
+ * ms_create, the set-up call, finds that array's address on the context's device.
+ *   ctx      : required (not NULL), from ms_create; its device and tuning table are used.
+ *   sizes    : n <= 262144 (4096 words per row) and at most 2^21 probe tiles (about 1e11
+ *              cells at the default tiles); larger matrices return MS_ERR_WORKSPACE_TOO_SMALL
+ *              before any HIP call.
+ * Every call on one GPU shares that GPU's array: calls that overlap on the device (different
+ * streams, or different contexts on the same GPU) race and must be serialised by the caller.
+ * The array keeps the last call's state; the search returns its header to zero at the end of
+ * every call, and the first call on a device, or a call after a failed launch, clears it with
+ * a small kernel first.
+ * Invalid: as ms_max_square, plus ctx NULL.
+ */
+ms_status ms_max_square_noalloc(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                                int64_t ld_words, ms_square *d_out, void *stream);
 
 /*
  * Full dp map of Section 2.1 eq. (1) into d_dp (int32, row stride ld_dp elements), plus the

@@ -22,7 +22,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "MaxsqError", "Square", "lib", "library_path", "ms_create", "ms_destroy", "ms_pack_u8",
-    "ms_max_square", "ms_square_map", "ms_square_map_from_max", "ms_batched_workspace_size", "ms_max_square_batched",
+    "ms_max_square", "ms_max_square_noalloc", "ms_square_map", "ms_square_map_from_max", "ms_batched_workspace_size", "ms_max_square_batched",
     "ms_set_config", "ms_get_config", "ms_candidate", "ms_num_candidates", "ms_autotune",
     "ms_autotune_save", "ms_autotune_load", "Context", "pack_u8", "max_square", "square_map",
     "max_square_batched", "square_map_from_max", "area", "words_per_row",
@@ -110,6 +110,7 @@ def lib():
             "ms_destroy": [_P],
             "ms_pack_u8": [_P, _P, _I64, _I64, _I64, _P, _I64, _P],
             "ms_max_square": [_P, _P, _I64, _I64, _I64, _P, _P],
+            "ms_max_square_noalloc": [_P, _P, _I64, _I64, _I64, _P, _P],
             "ms_square_map": [_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P],
             "ms_square_map_from_max": [_P, _P, _I64, _I64, _I64, _P, _P, _I64, _P],
             "ms_batched_workspace_size": [_P, _P, _I64, ctypes.POINTER(ctypes.c_size_t)],
@@ -163,6 +164,10 @@ def ms_pack_u8(ctx, d_a, m, n, ld_bytes, d_bits, ld_words, stream) -> int:
 
 def ms_max_square(ctx, d_bits, m, n, ld_words, d_out, stream) -> int:
     return lib().ms_max_square(ctx, d_bits, m, n, ld_words, d_out, stream)
+
+
+def ms_max_square_noalloc(ctx, d_bits, m, n, ld_words, d_out, stream) -> int:
+    return lib().ms_max_square_noalloc(ctx, d_bits, m, n, ld_words, d_out, stream)
 
 
 def ms_square_map(ctx, d_bits, m, n, ld_words, d_dp, ld_dp, d_out, stream) -> int:

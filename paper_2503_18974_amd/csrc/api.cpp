@@ -106,6 +106,14 @@ ms_status init_ctx(ms_ctx *c, int dev) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return MS_ERR_HIP;
     c->num_cus = cus > 0 ? cus : 256;
+    // set-up of the allocation-free search on this device (once per device), with the device
+    // current; the caller's current device is restored
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return MS_ERR_HIP;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) return MS_ERR_HIP;
+    const hipError_t se = mshost::noalloc_setup(dev);
+    if (prev != dev && hipSetDevice(prev) != hipSuccess) return MS_ERR_HIP;
+    if (se != hipSuccess) return MS_ERR_HIP;
     return MS_OK;
 }
 
@@ -352,6 +360,22 @@ ms_status ms_max_square(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
     std::lock_guard<std::mutex> lk(c->mu);
     return run_max_square(c, config_for(c, m, n), d_bits, m, n, ld_words, d_out,
                           (hipStream_t)stream);
+}
+
+ms_status ms_max_square_noalloc(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
+                                int64_t ld_words, ms_square *d_out, void *stream) {
+    ms_status s = validate_packed(d_bits, m, n, ld_words);
+    if (s != MS_OK) return s;
+    if (!ctx || !d_out) return MS_ERR_INVALID_ARGUMENT;
+    if (m > 0 && n > 0 && (cdiv(n, 64) > mshost::NOALLOC_MAX_WORDS ||
+                           mshost::max_probe_tiles(m, n) > mshost::NOALLOC_MAX_TILES))
+        return MS_ERR_WORKSPACE_TOO_SMALL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return MS_ERR_HIP;
+    const ms_config cfg = config_for(ctx, m, n);
+    mshost::LaunchEnv env{ctx->num_cus, (hipStream_t)stream};
+    return hip_status(mshost::launch_max_square_noalloc(env, ctx->device, cfg.probe_variant,
+                                                        d_bits, m, n, ld_words, d_out));
 }
 
 ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,

@@ -16,6 +16,7 @@
 // matrix in one grid-stride pass), k_batch_resolve (saturated tiles of every matrix),
 // k_batch_final (key -> result per matrix).
 #include <algorithm>
+#include <mutex>
 
 #include "device.hpp"
 #include "launch.hpp"
@@ -558,6 +559,13 @@ __global__ void k_write_result(ms_square *out, mshost::ScratchHeader *hdr, int64
     if (hdr && blockIdx.x == 0 && threadIdx.x == 0) hdr->result = ms_square{0, -1, -1};
 }
 
+// Zero a scratch header with plain stores (a kernel rather than a memset, so that a captured
+// graph replays it correctly).
+__global__ void k_clear_header(mshost::ScratchHeader *hdr) {
+    constexpr int W = (int)(sizeof(mshost::ScratchHeader) / sizeof(uint32_t));
+    if (threadIdx.x < W) reinterpret_cast<uint32_t *>(hdr)[threadIdx.x] = 0u;
+}
+
 // ---------------------------------------------------------------------------------- batched
 struct BatchCounters {
     uint32_t error;    // bit 1: the device prefix disagrees with the host's tile count
@@ -907,6 +915,11 @@ __global__ void k_write_i64(int64_t *dst, int64_t v) {
 
 } // namespace msk
 
+// Scratch of the allocation-free search (ms_max_square_noalloc), one copy per GPU, held until
+// the process ends.  Host code reaches it only through the device address that noalloc_setup
+// obtains: in host code this name is a host-side stand-in, not a device address.
+static __device__ __align__(256) unsigned char scratch[mshost::NOALLOC_SCRATCH_BYTES];
+
 // ====================================================================================== host
 namespace mshost {
 
@@ -1020,6 +1033,53 @@ hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHead
     hipLaunchKernelGGL(msk::k_write_result, dim3((unsigned)blocks), dim3(256), 0, env.stream, out,
                        hdr, count);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ allocation-free search
+// Per device: the address of `scratch` on that device (found once by noalloc_setup), and
+// whether its header may hold a failed call's state (true until the first call has cleared it).
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+static bool g_noalloc_dirty[NOALLOC_MAX_DEVICES] = {};
+
+hipError_t noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = p;
+    g_noalloc_dirty[device] = true;
+    return hipSuccess;
+}
+
+hipError_t launch_max_square_noalloc(const LaunchEnv &env, int device, int variant,
+                                     const uint64_t *bits, int64_t m, int64_t n, int64_t ldw,
+                                     ms_square *out) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    char *base = static_cast<char *>(g_noalloc_ptr[device]);  // never the array's host name
+    if (!base) return hipErrorNotInitialized;
+    auto *hdr = reinterpret_cast<ScratchHeader *>(base);
+    auto *state = reinterpret_cast<int32_t *>(base + 256);
+    auto *sat = reinterpret_cast<uint8_t *>(base + 256 + NOALLOC_STATE_BYTES);
+    hipError_t e = hipSuccess;
+    if (g_noalloc_dirty[device]) {
+        hipLaunchKernelGGL(msk::k_clear_header, dim3(1), dim3(64), 0, env.stream, hdr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        g_noalloc_dirty[device] = false;
+    }
+    if (m == 0 || n == 0) {
+        e = launch_write_result(env, out, hdr, 1);
+    } else {
+        // no per-tile bounds or box records: no map follows in this call
+        e = launch_max_square(env, variant, bits, m, n, ldw, hdr, state, sat, nullptr, nullptr,
+                              out);
+    }
+    if (e != hipSuccess) g_noalloc_dirty[device] = true;
+    return e;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

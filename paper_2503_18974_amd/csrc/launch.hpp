@@ -83,6 +83,22 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
 hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,
                                int64_t count);
 
+// Largest square without any allocation: the scratch is a fixed device array of the library
+// (one copy per GPU), laid out as a 256-byte header region | serial-pass state for
+// NOALLOC_MAX_WORDS words per row | NOALLOC_MAX_TILES saturation bytes.
+constexpr int64_t NOALLOC_MAX_WORDS = 4096;                   // n <= 262144
+constexpr int64_t NOALLOC_MAX_TILES = int64_t(1) << 21;       // max_probe_tiles(m, n) bound
+constexpr int64_t NOALLOC_STATE_BYTES = NOALLOC_MAX_WORDS * 64 * 2 * 4;
+constexpr int64_t NOALLOC_SCRATCH_BYTES = 256 + NOALLOC_STATE_BYTES + NOALLOC_MAX_TILES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+// Once per device, with that device current: find the device address of the array.
+hipError_t noalloc_setup(int device);
+// Enqueue the search on the array of `device` (set up before); clears the header first when
+// an earlier call on that device may have left it dirty.
+hipError_t launch_max_square_noalloc(const LaunchEnv &env, int device, int variant,
+                                     const uint64_t *bits, int64_t m, int64_t n, int64_t ldw,
+                                     ms_square *out);
+
 // Batched: workspace layout and launches.
 struct BatchLayout {
     size_t keys, prefix, counters, serial_state, flags, sat, total;

@@ -54,6 +54,10 @@ int main(void) {
     expect("max side field", ms_max_square(NULL, B, HUGE_SIDE, HUGE_SIDE, HUGE_SIDE / 64, &sq,
                                            NULL),
            MS_ERR_UNSUPPORTED);
+    expect("noalloc null ctx", ms_max_square_noalloc(NULL, B, 5, 5, 1, &sq, NULL),
+           MS_ERR_INVALID_ARGUMENT);
+    expect("noalloc m<0", ms_max_square_noalloc(NULL, B, -5, 5, 1, &sq, NULL),
+           MS_ERR_INVALID_ARGUMENT);
     expect("map null dp", ms_square_map(NULL, B, 5, 5, 1, NULL, 5, &sq, NULL),
            MS_ERR_INVALID_ARGUMENT);
     expect("map short ld_dp", ms_square_map(NULL, B, 5, 5, 1, &dp1, 4, &sq, NULL),
