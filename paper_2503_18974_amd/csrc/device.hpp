@@ -196,6 +196,9 @@ __device__ void dprun(const uint64_t *__restrict__ bits, int64_t ldw, int64_t n,
     const uint64_t lowmask = (1ull << b) - 1;  // the word's bits left of the lane's columns
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
+    // 1 <= ng <= NGMAX whatever the caller computed, so nww is 4..64 words and both loop steps
+    // below (rows per chunk, staging rows per pass) are at least one
+    ng = ng < 1 ? 1 : (ng > NGMAX ? NGMAX : ng);
     const int nww = ng * CPL;                    // window words
     const int rc_max = lds.cap / nww;            // rows per chunk
     const int fl_w = lane % nww, fl_r = lane / nww, fl_rpp = 64 / nww;
@@ -1026,6 +1029,7 @@ __device__ void dprun_block(const uint64_t *__restrict__ bits, int64_t ldw, int6
     const uint64_t lowmask = (1ull << b) - 1;
     const int64_t nwords = (n + 63) >> 6;
     const uint64_t lastmask = last_word_mask(n);
+    ng = ng < 1 ? 1 : (ng > 8 ? 8 : ng);  // 4..32 window words: every loop step below >= 1
     const int nww = ng * CPL;
     const int rc_max = BLK_WORDS / nww;
     const int fl_w = tid % nww, fl_r = tid / nww, fl_rpp = NTH / nww;
