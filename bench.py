@@ -133,9 +133,9 @@ def cpu_sections():
 
 
 def large_section(L, h, dev, names, reps, golden):
-    """Each large matrix packed in HBM: ms_max_square, ms_square_map (search + map in one call)
-    and ms_all_max_squares, each timed alone with HIP events after a 1 GiB write that evicts the
-    caches; the map's figures use ms_square_map's time minus ms_max_square's."""
+    """Each large matrix packed in HBM: ms_max_square, the map alone (ms_square_map_from_max on
+    that search's result), ms_square_map (search + map in one call) and ms_all_max_squares, each
+    timed alone with HIP events after a 1 GiB write that evicts the caches."""
     import ctypes
     import numpy as np
     import torch
@@ -177,7 +177,10 @@ def large_section(L, h, dev, names, reps, golden):
         torch.cuda.synchronize()
         if tuple(res2.cpu().tolist()) != got or int(dp.max().item()) != g["side"]:
             raise SystemExit("%s: ms_square_map result differs" % name)
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+        # each entry point timed on its own, caches flushed before each: the search; the map
+        # alone, from that search's result on the same context (one kernel, halos by region);
+        # the search and map in one call
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(reps)]
         for r in range(reps):
             flush.fill_(r & 0xff)
             ev[r][0].record(stream)
@@ -185,12 +188,19 @@ def large_section(L, h, dev, names, reps, golden):
             ev[r][1].record(stream)
             flush.fill_((r + 1) & 0xff)
             ev[r][2].record(stream)
-            L.ms_square_map(h, d.data_ptr(), m, n, ldw, dp.data_ptr(), n, res2.data_ptr(), sp)
+            L.ms_square_map_from_max(h, d.data_ptr(), m, n, ldw, res.data_ptr(), dp.data_ptr(),
+                                     n, sp)
             ev[r][3].record(stream)
+            flush.fill_((r + 2) & 0xff)
+            ev[r][4].record(stream)
+            L.ms_square_map(h, d.data_ptr(), m, n, ldw, dp.data_ptr(), n, res2.data_ptr(), sp)
+            ev[r][5].record(stream)
         torch.cuda.synchronize()
+        if int(dp.max().item()) != g["side"] or tuple(res2.cpu().tolist()) != got:
+            raise SystemExit("%s: timed calls changed the result" % name)
         t_p = sum(e[0].elapsed_time(e[1]) for e in ev) / reps * 1e-3
-        t_sm = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
-        t_m = max(t_sm - t_p, 1e-9)
+        t_m = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
+        t_sm = sum(e[4].elapsed_time(e[5]) for e in ev) / reps * 1e-3
         # all maximal squares (enumeration of every corner with dp = S), cold as above
         ws_n = ctypes.c_size_t()
         if L.ms_all_max_squares_workspace_size(h, m, n, ctypes.byref(ws_n)):
@@ -229,13 +239,17 @@ def large_section(L, h, dev, names, reps, golden):
                "map_us": t_m * 1e6, "map_gcells_s": cells / t_m / 1e9,
                "map_gbs": cells * MAP_BYTES_PER_CELL / t_m / 1e9,
                "map_frac": cells * MAP_BYTES_PER_CELL / t_m / 1e9 / HBM_PEAK_GBS,
+               "map_what": "ms_square_map_from_max alone (one k_dpmap launch), from the "
+                           "result of ms_max_square on the same context",
                "square_map_us": t_sm * 1e6,
-               "square_map_gcells_s": cells / t_sm / 1e9}
+               "square_map_gcells_s": cells / t_sm / 1e9,
+               "square_map_frac": cells * MAP_BYTES_PER_CELL / t_sm / 1e9 / HBM_PEAK_GBS}
         out[name] = rec
         log("large %s %dx%d S=%d: max_square %.1f us (%.0f Gcells/s), map %.1f us (%.0f GB/s, "
-            "%.0f%% of peak), all %d maximal squares %.1f us"
+            "%.0f%% of peak), search + map %.1f us (%.0f%%), all %d maximal squares %.1f us"
             % (name, m, n, g["side"], t_p * 1e6, rec["max_square_gcells_s"], t_m * 1e6,
-               rec["map_gbs"], 100 * rec["map_frac"], count, t_a * 1e6))
+               rec["map_gbs"], 100 * rec["map_frac"], t_sm * 1e6, 100 * rec["square_map_frac"],
+               count, t_a * 1e6))
         del d, dp
         torch.cuda.empty_cache()
     del flush
@@ -870,6 +884,16 @@ def main():
             "frac_of_achievable_write": achieved / extra["hbm_achievable"]["write_gbs"],
         },
     }
+    if "large" in extra:
+        out["roofline_large"] = {
+            "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "kernel": "k_dpmap (ms_square_map_from_max after ms_max_square on the same context)",
+            "bytes_per_cell": MAP_BYTES_PER_CELL,
+            "timed": "HIP events around each call on its stream, caches flushed before it",
+            "per_matrix": {k: {"achieved": v["map_gbs"], "frac": v["map_frac"],
+                               "avg_launch_us": v["map_us"],
+                               "square_map_end_to_end_frac": v["square_map_frac"]}
+                           for k, v in extra["large"].items()}}
     if graph_value is not None:
         extra["graph_step_gcells_s"] = graph_value
     if multi is not None:

@@ -144,6 +144,10 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
  * (device or pinned host memory) must hold the ms_square that ms_max_square wrote for the same
  * d_bits, m, n; only its side is read, and it sets the bands' and windows' head start, so a
  * smaller side than the true one gives a wrong map.  Saves the search when both are wanted.
+ * When d_max is the very result buffer of the last search run on this context (ms_max_square
+ * or ms_square_map, same d_bits, m, n, ld_words, no other search on the context since), that
+ * search's per-tile bounds are still in the context and the map sizes its halos by region, as
+ * ms_square_map does; otherwise every band and window starts S rows / columns early.
  * Invalid: as ms_square_map, plus d_max NULL.
  */
 ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,

@@ -81,6 +81,15 @@ struct ms_ctx {
     // pinned host words through which the cube search reads its device flags
     uint64_t *pinned = nullptr;
     bool rect_dirty = false;
+    // The last search run on this context's scratch: its per-tile bounds and large-tile box
+    // stay there until the next search, so a map of the same matrix that is handed this
+    // search's result can size its halos by region (see ms_square_map_from_max).
+    struct {
+        const uint64_t *bits = nullptr;
+        int64_t m = -1, n = -1, ldw = -1;
+        const ms_square *out = nullptr;
+        int variant = -1;
+    } last;
     std::mutex mu;
 };
 
@@ -211,6 +220,7 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
         c->scratch = nullptr;
+        c->last.out = nullptr;  // the bounds went with the old scratch
     }
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
@@ -263,6 +273,7 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
     if (s != MS_OK) return s;
     mshost::LaunchEnv env{c->num_cus, stream};
     hipError_t e;
+    c->last.out = nullptr;
     if (m == 0 || n == 0) {
         e = mshost::launch_write_result(env, out, hdr_of(c), out ? 1 : 0);
     } else {
@@ -273,6 +284,14 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
     if (e != hipSuccess) {
         c->dirty = true;
         return hip_status(e);
+    }
+    if (m > 0 && n > 0) {
+        c->last.bits = bits;
+        c->last.m = m;
+        c->last.n = n;
+        c->last.ldw = ldw;
+        c->last.out = out;
+        c->last.variant = cfg.probe_variant;
     }
     return MS_OK;
 }
@@ -426,8 +445,18 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
     s = ensure_scratch(c, m, n, st);
     if (s != MS_OK) return s;
     mshost::LaunchEnv env{c->num_cus, st};
+    // d_max is the result of this context's last search, on these bits: that search's per-tile
+    // bounds are still in the scratch (calls on a context are ordered on one stream), so the
+    // halos follow them as in ms_square_map
+    const bool same = c->last.out != nullptr && c->last.out == d_max && c->last.bits == d_bits &&
+                      c->last.m == m && c->last.n == n && c->last.ldw == ld_words &&
+                      c->last.variant == cfg.probe_variant;
+    const mshost::MapRegions regions{bounds_of(c), mshost::probe_tile_rows(cfg.probe_variant),
+                                     cdiv(cdiv(n, 64), mshost::PROBE_TILE_WORDS),
+                                     hdr_of(c)->big_box};
     return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m,
-                                                n, ld_words, d_dp, ld_dp, d_max, state_of(c)));
+                                                n, ld_words, d_dp, ld_dp, d_max, state_of(c),
+                                                same ? &regions : nullptr));
 }
 
 ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_t count,

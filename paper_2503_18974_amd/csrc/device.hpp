@@ -556,8 +556,11 @@ struct SatBatch {
 // Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
 // key with the first owned cell of E_k.  Returns an upper bound on the tile's largest side (exact
 // unless the search stopped early because the tile could not reach the best side so far), or
-// SAT_BOUND when E_KC is non-empty among the owned cells ("saturated": the resolve pass,
-// resolve_tile, finishes such a tile).
+// SAT_BOUND when E_KC is non-empty among the owned cells ("saturated": the resolve pass finishes
+// such a tile).  A saturated tile pushes a lower bound instead: the largest k whose erosion,
+// continued past the halo inside the register tile, still holds an owned cell.  Its corner is a
+// real cell with dp >= k; the exact pass later pushes the true first cell, which wins the key
+// (same side, smaller position) or a larger side.
 template <class TS>
 __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int64_t ty, int64_t tx, const TileSink &sink) {
@@ -594,33 +597,49 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
     const int64_t best = key_side(load_relaxed(sink.key));
     if (!any_owned<TS>(E, rg, lane_ok)) return 0;
 
-    int cur = 1;
-    bool saturated = true;
-    while (cur < TS::KC) {
-        erode_by<RPL>(E, T, cur, rg, wl);
-        if (any_owned<TS>(T, rg, lane_ok)) {
+    // One loop, one erosion call site (each call site inlines the erosion bodies, and the
+    // register tile leaves little room): E holds E_cur, the step tries E_{cur + d} (d <= cur).
+    //   phase 0: doubling, d = cur, until E_{2 cur} is empty or cur reaches KC;
+    //   phase 1 (saturated): steps of DMAX rows while non-empty, inside the register tile, for a
+    //            lower bound past the halo (what lies above or left of the tile reads as zero,
+    //            so what survives is a subset of the true E_k: a real square);
+    //   phase 2: halving steps.  Unsaturated tiles stop as soon as their bracket cannot reach
+    //            the best side published so far.
+    constexpr int DMAX = TS::RPL < 16 ? TS::RPL : 16;
+    int cur = 1, d = 1, phase = 0;
+    bool saturated = false;
+    for (;;) {
+        erode_by<RPL>(E, T, d, rg, wl);
+        const bool ok = any_owned<TS>(T, rg, lane_ok);
+        if (ok) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) E[r] = T[r];
-            cur <<= 1;
-        } else {
-            saturated = false;
-            break;
+            cur += d;
         }
-    }
-    if (!saturated) {
-        // the tile's side is in [cur, 2 cur - 1]; skip it if it cannot reach the best so far
-        if (2 * cur - 1 < best) return 2 * cur - 1;
-        for (int d = cur >> 1; d >= 1; d >>= 1) {
-            erode_by<RPL>(E, T, d, rg, wl);
-            if (any_owned<TS>(T, rg, lane_ok)) {
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) E[r] = T[r];
-                cur += d;
+        if (phase == 0) {
+            if (!ok) {  // the tile's side is in [cur, 2 cur - 1]
+                if (2 * cur - 1 < best) return 2 * cur - 1;
+                phase = 2;
+                d = cur >> 1;
+            } else if (cur >= TS::KC) {
+                saturated = true;
+                phase = cur + DMAX <= TS::ROWS ? 1 : 2;
+                d = phase == 1 ? DMAX : DMAX >> 1;
+            } else {
+                d = cur;
             }
-            if (cur + d - 1 < best) return cur + d - 1;
+        } else if (phase == 1) {
+            if (!ok || cur + DMAX > TS::ROWS) {
+                phase = 2;
+                d = DMAX >> 1;
+            }
+        } else {
+            if (!saturated && cur + d - 1 < best) return cur + d - 1;
+            d >>= 1;
         }
-        if (cur < best) return cur;
+        if (d == 0) break;
     }
+    if (!saturated && cur < best) return cur;
     // first owned cell of E_cur in row-major order
     int64_t pos = INT64_MAX;
     if (lane_ok) {
@@ -737,6 +756,35 @@ __device__ __forceinline__ bool row_test(const uint64_t (&P)[HB], int32_t k, uin
     return true;
 }
 
+// The first row of a stretch of rows: the largest k <= kmax such that an owned cell of the
+// row has dp >= k, searched upwards from g (the best side any tile had published): sides below
+// g cannot change the result.  Returns g - 1 with *pos = -1 when no cell of the row reaches g
+// (g >= 2); otherwise the row's largest side, with *pos = i * n + its first column.
+__device__ __forceinline__ int32_t first_row_search(const uint64_t (&P)[HB], int32_t g,
+                                                    int32_t kmax, uint64_t own, int lane,
+                                                    int64_t w0, int64_t i, int64_t n,
+                                                    int64_t *pos) {
+    // one search loop, one row_test call site: gallop from g - 1 (treated as reached) by steps
+    // of 1, 2, 4, ..., then bisect between the last success lo and the first failure hi
+    int32_t lo = g >= 2 ? g - 1 : 0, hi = kmax + 1, step = 1;
+    bool gallop = true;
+    *pos = -1;
+    while (hi - lo > 1) {
+        int32_t k = gallop ? lo + step : (lo + hi) >> 1;
+        k = k < hi ? k : hi - 1;
+        int64_t col = 0;
+        if (row_test(P, k, own, lane, w0, &col)) {
+            lo = k;
+            *pos = i * n + col;
+            step <<= 1;
+        } else {
+            hi = k;
+            gallop = false;
+        }
+    }
+    return lo;
+}
+
 // Consecutive set saturation bytes at idx0, idx0 - step, idx0 - 2 step, ... (idx0 - k step >= 0
 // while k < limit), 64 per round.
 __device__ __forceinline__ int64_t sat_run(const uint8_t *__restrict__ sat, int64_t idx0,
@@ -760,7 +808,7 @@ __device__ __forceinline__ int64_t sat_run(const uint8_t *__restrict__ sat, int6
 template <class TS>
 __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
                              int64_t ldw, int64_t ra, int64_t rb, int64_t txa, int64_t txb,
-                             int64_t U, int32_t *best_out, int64_t *bpos_out) {
+                             int64_t U, int32_t g, int32_t *best_out, int64_t *bpos_out) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
     const int64_t xa = txa * OWN_COLS;
@@ -814,7 +862,7 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
     }
     // the tile's rows, FB at a time
     int32_t best = 0;
-    int64_t bpos = 0;
+    int64_t bpos = -1;
     for (int64_t i0 = ra; i0 < rb; i0 += FB) {
         uint64_t v[FB];
 #pragma unroll
@@ -831,25 +879,7 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
             for (int p = 0; p < HB; ++p) P[p] &= x;
             int64_t col = 0;
             if (i == ra) {
-                int32_t lo = 0, k = 1;
-                int64_t lo_col = 0;
-                while (k <= U + TS::TR && row_test(P, k, own, lane, w0, &col)) {
-                    lo = k;
-                    lo_col = col;
-                    k <<= 1;
-                }
-                int32_t hi = k < U + TS::TR + 1 ? k : (int32_t)(U + TS::TR + 1);
-                while (hi - lo > 1) {
-                    const int32_t mid = (lo + hi) >> 1;
-                    if (row_test(P, mid, own, lane, w0, &col)) {
-                        lo = mid;
-                        lo_col = col;
-                    } else {
-                        hi = mid;
-                    }
-                }
-                best = lo;
-                bpos = i * n + lo_col;
+                best = first_row_search(P, g, (int32_t)(U + TS::TR), own, lane, w0, i, n, &bpos);
             } else if (row_test(P, best + 1, own, lane, w0, &col)) {
                 ++best;
                 bpos = i * n + col;
@@ -906,8 +936,8 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
     for (;;) {
         U = U < ucap ? U : ucap;
         int32_t best = 0;
-        int64_t bpos = 0;
-        if (!resolve_pass<TS>(bits, m, n, ldw, ra, rb, tx, tx, U, &best, &bpos)) {
+        int64_t bpos = -1;
+        if (!resolve_pass<TS>(bits, m, n, ldw, ra, rb, tx, tx, U, (int32_t)g, &best, &bpos)) {
             // the serial pass finishes the matrix; serial_count counts the matrices so flagged
             if (lane == 0 && atomicOr(serial_flag, 1u) == 0u && serial_count)
                 atomicAdd(serial_count, 1u);
@@ -915,7 +945,7 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
         }
         best = uniform(best);
         if (best < U || U >= ucap) {
-            if (lane == 0 && best > 0) atomicMax(key, make_key(best, bpos));
+            if (lane == 0 && best > 0 && bpos >= 0) atomicMax(key, make_key(best, bpos));
             note_bound(bounds, ty * ntx + tx, best);
             return;
         }
@@ -976,17 +1006,230 @@ __device__ uint32_t resolve_group(const uint64_t *__restrict__ bits, int64_t m, 
     for (;;) {
         U = U < ucap ? U : ucap;
         int32_t best = 0;
-        int64_t bpos = 0;
-        if (!fits(U) || !resolve_pass<TS>(bits, m, n, ldw, ta, tb, lo, hi, U, &best, &bpos))
+        int64_t bpos = -1;
+        if (!fits(U) ||
+            !resolve_pass<TS>(bits, m, n, ldw, ta, tb, lo, hi, U, (int32_t)g, &best, &bpos))
             return live;
         best = uniform(best);
         if (best < U || U >= ucap) {
-            if (lane == 0 && best > 0) atomicMax(key, make_key(best, bpos));
+            if (lane == 0 && best > 0 && bpos >= 0) atomicMax(key, make_key(best, bpos));
             for (uint32_t b = live; b; b &= b - 1)
                 note_bound(bounds, ty * ntx + tx0 + (__ffs(b) - 1), best);
             return 0;
         }
         U = 2 * (int64_t)best;
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// resolve_tile_block: a saturated tile finished by the NW waves of a block together.
+//
+// One wave alone spends most of a tile's time in chains of dependent steps (the upward height
+// scan, then one row test after another), so here the block splits both.  The rows above the
+// tile, [ta - U, ta), are cut into NW segments and the tile's own rows into NW parts, one of
+// each per wave.  Each wave scans its segment and its part once, bottom to top, giving per
+// column F (every row of the piece is one) and B (the run of ones ending at the piece's last
+// row, bit-sliced like the heights).  Heights then flow down the pieces in order, top to
+// bottom, through LDS: H after a piece is F ? H before + its length : B.  The wave owning
+// part p takes the heights at the row above its part from that chain and runs the row tests
+// of its rows only.  Every part is exact for its own rows (its heights are those of a scan
+// starting U rows above the tile); the block's largest side decides, as in resolve_tile,
+// whether U was deep enough.
+//
+// The first row of a part searches upward from g, the best side any tile had published when
+// the block started: sides below g cannot change the result, so a part whose rows never reach
+// g reports g - 1 as its bound and nothing to the key.  Later rows test best + 1 only (the
+// running maximum grows by at most one per row).
+// ----------------------------------------------------------------------------------------------
+constexpr int RESOLVE_WAVES = 4;  // waves per block in k_resolve, one part of a tile each
+
+struct ResolveLds {
+    uint64_t H[HB][WAVE];        // heights at the bottom of the last piece folded in
+    int32_t best[RESOLVE_WAVES];
+    int64_t scal[2];             // the tile's bound and the best side, for the whole block
+};
+
+// Scan rows [sa, sb) of the lane's word upwards: F = columns that are one in every row,
+// B = per column, the run of ones ending at row sb - 1 (clamped at the piece's length).
+__device__ __forceinline__ void piece_scan(const uint64_t *__restrict__ bits, int64_t ldw,
+                                           int64_t wl_c, uint64_t wmask, int64_t sa, int64_t sb,
+                                           uint64_t &F, uint64_t (&B)[HB]) {
+#pragma unroll
+    for (int p = 0; p < HB; ++p) B[p] = 0;
+    uint64_t acc = wmask;
+    // row pointers are wave-uniform, the lane's word a 32-bit offset: no 64-bit address per load
+    const uint32_t wo = (uint32_t)wl_c;
+    constexpr int FB = 8;  // rows per round, the next round's loads issued before counting
+    uint64_t nv[FB];
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+        const int64_t r = sb - 1 - u >= sa ? sb - 1 - u : sa;  // clamped: the loads batch
+        nv[u] = sa < sb ? (bits + r * ldw)[wo] : 0ull;
+    }
+    for (int64_t r0 = sb - 1; r0 >= sa; r0 -= FB) {
+        uint64_t v[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) v[u] = nv[u];
+        if (r0 - FB >= sa) {
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int64_t r = r0 - FB - u >= sa ? r0 - FB - u : sa;
+                nv[u] = (bits + r * ldw)[wo];
+            }
+        }
+        for (int u = 0; u < FB; ++u) {  // stops at the piece's top: not unrolled
+            if (r0 - u < sa) break;
+            acc &= v[u] & wmask;
+            planes_inc_masked(B, acc);
+        }
+        if (!__ballot(acc != 0)) break;
+    }
+    F = acc;
+}
+
+// One step of the chain: H = the heights in LDS (zero for the first piece); LDS <- F ? H + len :
+// B; on return B holds H (the heights above the piece).
+__device__ __forceinline__ void chain_step(ResolveLds &L, int lane, bool has_prev, uint64_t F,
+                                           uint64_t (&B)[HB], int64_t len) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int p = 0; p < HB; ++p) {
+        const uint64_t a = has_prev ? L.H[p][lane] : 0ull;
+        const uint64_t sum = (len >> p) & 1 ? ~(a ^ c) : (a ^ c);
+        c = (len >> p) & 1 ? (a | c) : (a & c);
+        L.H[p][lane] = (F & sum) | (~F & B[p]);
+        B[p] = a;
+    }
+}
+
+template <class TS, int NW>
+__device__ void resolve_tile_block(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
+                                   int64_t ldw, int64_t ty, int64_t tx, int64_t ntx,
+                                   const uint8_t *__restrict__ sat, unsigned long long *key,
+                                   uint32_t *serial_flag, int32_t *bounds, ResolveLds &L) {
+    constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
+    const int lane = __lane_id();
+    const int wv = uniform((int32_t)(threadIdx.x / WAVE));  // wave-uniform: keep it scalar
+    m = uniform(m);
+    n = uniform(n);
+    ldw = uniform(ldw);
+    ty = uniform(ty);
+    tx = uniform(tx);
+    const int64_t t = ty * ntx + tx;
+    const int64_t ta = ty * TS::TR, tb = ta + TS::TR < m ? ta + TS::TR : m;
+    const int64_t mn = m < n ? m : n;
+    if (wv == 0) {
+        const int64_t vrun = uniform(sat_run(sat, t, ntx, ty + 1, lane));
+        const int64_t hrun = uniform(sat_run(sat, t, 1, tx + 1, lane));
+        int64_t u = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
+        u = u < mn ? u : mn;
+        const int64_t g0 = uniform(key_side(load_relaxed(key)));
+        if (lane == 0) {
+            L.scal[0] = u;
+            L.scal[1] = g0;
+        }
+    }
+    __syncthreads();
+    const int64_t ucap = uniform(L.scal[0]);
+    const int64_t g = uniform(L.scal[1]);
+    __syncthreads();  // the next tile rewrites scal
+    if (ucap < g) {   // cannot reach the best side found so far
+        if (wv == 0) note_bound(bounds, t, ucap);
+        return;
+    }
+    const int64_t xa = tx * OWN_COLS, xb = (tx + 1) * OWN_COLS < n ? (tx + 1) * OWN_COLS : n;
+    const auto fits = [&](int64_t U) {
+        const int64_t w0 = xa - U > 0 ? ((xa - U) >> 6) : 0;
+        return ((xb + 63) >> 6) - w0 <= WAVE && U + TS::TR + 1 < (1 << HB);
+    };
+    // one pass at the bound when its window fits (exact at once), else doubling from twice the
+    // best side so far
+    int64_t U = fits(ucap) ? ucap : 2 * (g > TS::KC ? g : TS::KC);
+    const int64_t prow = (TS::TR + NW - 1) / NW;
+    const int64_t ra = uniform(ta + wv * prow < tb ? ta + wv * prow : tb);
+    const int64_t rb = uniform(ra + prow < tb ? ra + prow : tb);
+    const int64_t nwords = (n + 63) >> 6;
+    for (;;) {
+        U = U < ucap ? U : ucap;
+        if (!fits(U)) {  // the serial pass finishes the matrix
+            if (wv == 0 && lane == 0) atomicOr(serial_flag, 1u);
+            return;
+        }
+        const int64_t w0 = xa - U > 0 ? ((xa - U) >> 6) : 0;
+        const int64_t w1 = (xb + 63) >> 6;
+        const int64_t wl = w0 + lane;
+        const bool valid = wl < w1;
+        const int64_t wl_c = valid ? wl : w0;
+        const uint64_t wmask = !valid ? 0ull : (wl == nwords - 1 ? last_word_mask(n) : ~0ull);
+        uint64_t own = 0;
+        if (valid) {
+            const int64_t lo = (xa > wl * 64 ? xa : wl * 64) - wl * 64;
+            const int64_t hi = (xb < wl * 64 + 64 ? xb : wl * 64 + 64) - wl * 64;
+            if (hi > lo) own = (hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1)) << lo;
+        }
+        // this wave's segment above the tile and its part of the tile
+        const int64_t rstop = ta - U > 0 ? ta - U : 0;
+        const int64_t seg = (ta - rstop + NW - 1) / NW;
+        const int64_t sa = uniform(rstop + wv * seg < ta ? rstop + wv * seg : ta);
+        const int64_t sb = uniform(sa + seg < ta ? sa + seg : ta);
+        // the chain: segments 0 .. NW-1, then parts 0 .. NW-1, each folded by its wave in turn
+        // (a part is scanned only once the segments are folded, so the two scans' registers
+        // are never live together)
+        uint64_t F, P[HB];
+        piece_scan(bits, ldw, wl_c, wmask, sa, sb, F, P);
+        for (int s = 0; s < NW; ++s) {
+            __syncthreads();
+            if (s == wv) chain_step(L, lane, s > 0, F, P, sb - sa);
+        }
+        // then the part: P ends as the heights at row ra - 1, read from the chain before the
+        // part is folded in
+        piece_scan(bits, ldw, wl_c, wmask, ra, rb, F, P);
+        for (int s = 0; s < NW; ++s) {
+            __syncthreads();
+            if (s == wv) chain_step(L, lane, true, F, P, rb - ra);
+        }
+        // the part's rows: the first searched upwards from g, the rest tested at best + 1
+        const int32_t kmax = (int32_t)(U + TS::TR);
+        int32_t best = 0;
+        int64_t bpos = -1;
+        constexpr int FB = 8;
+        for (int64_t i0 = ra; i0 < rb; i0 += FB) {
+            uint64_t v[FB];
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const int64_t r = i0 + u < rb ? i0 + u : rb - 1;
+                v[u] = (bits + r * ldw)[(uint32_t)wl_c];
+            }
+            for (int u = 0; u < FB; ++u) {
+                const int64_t i = i0 + u;
+                if (i >= rb) break;
+                const uint64_t x = v[u] & wmask;
+                planes_inc_masked(P, ~0ull);
+#pragma unroll
+                for (int p = 0; p < HB; ++p) P[p] &= x;
+                int64_t col = 0;
+                if (i == ra) {
+                    best = first_row_search(P, (int32_t)g, kmax, own, lane, w0, i, n, &bpos);
+                } else if (row_test(P, best + 1, own, lane, w0, &col)) {
+                    ++best;
+                    bpos = i * n + col;
+                }
+            }
+        }
+        best = uniform(best);
+        if (lane == 0) L.best[wv] = best;
+        __syncthreads();
+        int32_t bmax = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) bmax = L.best[w] > bmax ? L.best[w] : bmax;
+        bmax = uniform(bmax);
+        __syncthreads();  // L.best is rewritten by the next pass
+        if (bmax < U || U >= ucap) {
+            if (lane == 0 && best > 0 && bpos >= 0 && best >= g) atomicMax(key, make_key(best, bpos));
+            if (wv == 0) note_bound(bounds, t, bmax);
+            return;
+        }
+        U = 2 * (int64_t)bmax;
     }
 }
 

@@ -5,7 +5,7 @@
 //                its exact side (up to the side its halo certifies) with its first corner into
 //                one atomic key, and writes a saturation byte: 1 when it holds a larger square.
 //   k_resolve  : if any tile saturated, finishes those tiles exactly with column heights and a
-//                per-row test (device.hpp resolve_tile / resolve_group); the last wave to
+//                per-row test (device.hpp resolve_tile_block, one block per tile); the last wave to
 //                finish (or, with no saturated tile, the first wave) turns the key into the
 //                result (running the serial pass for a square too wide for the resolve pass)
 //                and clears the scratch.
@@ -206,45 +206,53 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
     }
 }
 
-// After the probe: if any tile saturated, finish those tiles exactly (resolve_tile, or
-// resolve_group for neighbouring tiles), spread over the waves so that clustered saturated tiles
-// land on different waves; the last wave to finish (a completion count, no waiting) writes the
-// result.  With no saturated tile, the first wave writes it at once and every other wave returns.
-// The wave that writes the result also folds the probe blocks' large-tile box records.
-// Waves sharing one saturated tile in k_resolve (a divisor of the 4 waves of a block).
-constexpr int RESOLVE_PARTS = 4;
-// Neighbouring tile columns one wave resolves together when many tiles saturate (at most 32).
-// On a 16384^2 blob image (2804 of 3042 tiles saturated) the search takes 440 us one tile per
-// wave and 339 / 343 / 355 us with groups of 2 / 3 / 4: the gain is having every group in
-// flight at once, and smaller groups keep each tile's recorded bound tighter.
+// After the probe: if any tile saturated, finish those tiles exactly, then the last wave to
+// finish (a completion count, no waiting) writes the result.  With no saturated tile, the first
+// wave writes it at once and every other wave returns.  The wave that writes the result also
+// folds the probe blocks' large-tile box records.
+//  * Few saturated tiles (at most one per block: wide squares, whose tiles have long height
+//    scans): one block of RESOLVE_WAVES waves per tile (resolve_tile_block), tiles dealt to
+//    blocks by index modulo the grid so that clustered tiles land on different blocks.
+//  * Many (blob images): one wave per RESOLVE_GROUP neighbouring tiles of a tile row
+//    (resolve_group), sharing one window and one height scan; there the work, not the length
+//    of each chain, is what costs, and one wave per group does the least of it.
+// Neighbouring tile columns one wave resolves together in the second case (at most 32).  On a
+// 16384^2 blob image (2804 of 3042 tiles saturated) the search takes 440 us one tile per wave
+// and 339 / 343 / 355 us with groups of 2 / 3 / 4.
 constexpr int RESOLVE_GROUP = 2;
 
 template <class TS>
-__global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bits, int64_t m,
-                                                 int64_t n, int64_t ldw, int64_t ntiles,
-                                                 int64_t ntx, mshost::ScratchHeader *hdr,
-                                                 const uint8_t *__restrict__ sat,
-                                                 int32_t *__restrict__ bounds,
-                                                 const uint32_t *__restrict__ box_rec,
-                                                 int64_t nrec, int32_t *serial_state,
-                                                 ms_square *out) {
+__global__ __launch_bounds__(64 * RESOLVE_WAVES) void k_resolve(
+    const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw, int64_t ntiles,
+    int64_t ntx, mshost::ScratchHeader *hdr, const uint8_t *__restrict__ sat,
+    int32_t *__restrict__ bounds, const uint32_t *__restrict__ box_rec, int64_t nrec,
+    int32_t *serial_state, ms_square *out) {
+    __shared__ ResolveLds L;
     const int lane = __lane_id();
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int64_t nblk = gridDim.x;
     const uint32_t nsat = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->nsat));
     if (nsat == 0) {
         if (wave == 0) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec);
         return;
     }
-    // With few saturated tiles (a wide square: each one's height scan is long and there are
-    // waves to spare) RESOLVE_PARTS waves share each tile, part = wave % parts taking a slice of
-    // its rows, groups of `parts` waves taking tiles g, g + ngroups, ... (64 saturation bytes
-    // per round); with many (blob images) one wave takes whole tiles, RESOLVE_GROUP neighbours
-    // at a time, since every part would repeat the scan of the rows above.
-    const int parts = (int64_t)nsat * RESOLVE_PARTS <= nwave ? RESOLVE_PARTS : 1;
-    if (parts == 1) {
-        // many saturated tiles: RESOLVE_GROUP neighbouring tile columns of a tile row per wave,
-        // sharing one window and one height scan (resolve_group)
+    if ((int64_t)nsat <= nblk) {
+        // saturated tiles t = blockIdx.x + k * gridDim.x, found 64 at a time; every wave of the
+        // block reads the same bytes, so the block agrees on its sequence of tiles
+        for (int64_t base = blockIdx.x; base < ntiles; base += 64 * nblk) {
+            const int64_t t = base + (int64_t)lane * nblk;
+            uint64_t b = __ballot(t < ntiles && sat[t] != 0);
+            while (b) {
+                const int l = __ffsll((long long)b) - 1;
+                b &= b - 1;
+                const int64_t tt = base + (int64_t)l * nblk;
+                const int64_t ty = tt / ntx, tx = tt - ty * ntx;
+                resolve_tile_block<TS, RESOLVE_WAVES>(bits, m, n, ldw, ty, tx, ntx, sat,
+                                                      &hdr->key, &hdr->serial_flag, bounds, L);
+            }
+        }
+    } else {
         const int64_t ngx = (ntx + RESOLVE_GROUP - 1) / RESOLVE_GROUP;
         const int64_t ngroups = (ntiles / ntx) * ngx;
         for (int64_t base = wave; base < ngroups; base += 64 * nwave) {
@@ -268,20 +276,6 @@ __global__ __launch_bounds__(256) void k_resolve(const uint64_t *__restrict__ bi
                     resolve_tile<TS>(bits, m, n, ldw, gy, tx0 + (__ffs(rest) - 1), ntx, sat,
                                      &hdr->key, &hdr->serial_flag, bounds);
             }
-        }
-    }
-    const int64_t grp = wave / parts, ngrp = nwave / parts;
-    const int part = (int)(wave % parts);
-    for (int64_t base = grp; parts > 1 && base < ntiles; base += 64 * ngrp) {
-        const int64_t t = base + (int64_t)lane * ngrp;
-        uint64_t b = __ballot(t < ntiles && sat[t] != 0);
-        while (b) {
-            const int l = __ffsll((long long)b) - 1;
-            b &= b - 1;
-            const int64_t tt = base + (int64_t)l * ngrp;
-            const int64_t ty = tt / ntx, tx = tt - ty * ntx;
-            resolve_tile<TS>(bits, m, n, ldw, ty, tx, ntx, sat, &hdr->key, &hdr->serial_flag,
-                             bounds, part, parts);
         }
     }
     __threadfence();
@@ -967,9 +961,11 @@ static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits
                        m, n, ldw, ntiles, ntx, hdr, sat, bounds, box_rec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t rblocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 8),
-                                                                    (int64_t)env.num_cus * 2));
-    hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks), dim3(256), 0, env.stream,
+    // one block per saturated tile when they are few, each block several tiles when many
+    const int64_t rblocks = std::max<int64_t>(1, std::min<int64_t>(ntiles,
+                                                                    (int64_t)env.num_cus * 4));
+    hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks),
+                       dim3(64 * msk::RESOLVE_WAVES), 0, env.stream,
                        bits, m, n, ldw, ntiles, ntx, hdr, sat, bounds, box_rec, blocks,
                        serial_state, out);
     return hipGetLastError();

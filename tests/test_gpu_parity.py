@@ -234,8 +234,11 @@ def test_resolve_falls_back_to_serial(dev):
 
 @pytest.mark.parametrize("side", [300, 449, 700, 1500, 2100])
 def test_map_from_max_wide(dev, side):
-    """The map from an earlier search's device result (no per-tile bounds): the 2048-column
-    block kernel for 448 < S <= 1984, the one-wave sweep beyond, the narrow kernel below."""
+    """The map from an earlier search's device result, in both of its forms: handed the
+    search's own result buffer (the context still holds that search's per-tile bounds, so the
+    halos follow them) and a copy of it (no per-tile bounds: one S halo everywhere).  The
+    2048-column block kernel for 448 < S <= 1984, the one-wave sweep beyond, the narrow kernel
+    below."""
     import torch
     announce("map_from_max", side)
     rng = np.random.default_rng([side, 11])
@@ -244,12 +247,15 @@ def test_map_from_max_wide(dev, side):
     r0, c0 = int(rng.integers(0, m - side)), int(rng.integers(0, n - side))
     a[r0:r0 + side, c0:c0 + side] = 1
     d = to_dev_bits(oracle.pack(a), dev)
+    ref_dp, ref = oracle.square_map(a)
     res = M.max_square(d, n, sync=False)
     dp = torch.full((m, n), -7, dtype=torch.int32, device=dev)
-    M.square_map_from_max(d, n, res, dp=dp)
-    ref_dp, ref = oracle.square_map(a)
+    M.square_map_from_max(d, n, res, dp=dp)           # by region
     assert tuple(res.cpu().tolist()) == ref
     np.testing.assert_array_equal(dp.cpu().numpy(), ref_dp)
+    dp2 = torch.full((m, n), -7, dtype=torch.int32, device=dev)
+    M.square_map_from_max(d, n, res.clone(), dp=dp2)  # one halo
+    np.testing.assert_array_equal(dp2.cpu().numpy(), ref_dp)
 
 
 @pytest.mark.parametrize("spots", [1, 3])
