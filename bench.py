@@ -674,17 +674,33 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     value = cells * args.steps / elapsed / 1e9
-    # roofline: the same steps again with HIP events around every map call on its stream (an
-    # event record between launches costs a few microseconds, so it is kept out of `value`)
+    # roofline: the map kernel's average launch duration, from HIP events around K passes of
+    # the 45 map calls back to back on the launch stream (each from its matrix's search result
+    # of the steps above); an event pair around every single call would add each launch's
+    # start-up gap to it
+    def maps_only():
+        for (n, pa, pb, ldw, pdp, pres) in calls:
+            if L.ms_square_map_from_max(h, pb, n, n, ldw, pres, pdp, n, sp):
+                raise RuntimeError("ms_square_map_from_max failed")
+
+    maps_only()
+    torch.cuda.synchronize()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    for k in range(args.steps):
+        maps_only()
+    r1.record(stream)
+    torch.cuda.synchronize()
+    map_launches = len(mats) * args.steps
+    map_avg_ms = r0.elapsed_time(r1) / map_launches
+    # the same steps with events around every map call, for comparison (kept out of `value`)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
     instrumented_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    map_ms = sum(e0.elapsed_time(e1) for evs in ev for e0, e1 in evs)
-    map_launches = len(mats) * args.steps
-    map_avg_ms = map_ms / map_launches
+    map_each_avg_ms = sum(e0.elapsed_time(e1) for evs in ev for e0, e1 in evs) / map_launches
     map_bytes_avg = MAP_BYTES_PER_CELL * cells / len(mats)
     achieved = map_bytes_avg / (map_avg_ms * 1e-3) / 1e9
     log("step %.3f ms, %.1f Gcells/s; dp-map avg %.1f us -> %.0f GB/s"
@@ -876,8 +892,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": stored_traffic(),
             "avg_launch_us": map_avg_ms * 1e3,
-            "timed_region": "%d further single-stream steps with events around every map call "
-                            "on its stream (%.3f ms/step)" % (args.steps, instrumented_ms),
+            "timed_region": "%d passes of the 45 map calls back to back on the launch stream, "
+                            "HIP events around the whole region" % args.steps,
+            "avg_call_us_events_each": map_each_avg_ms * 1e3,
+            "events_each_region": "%d single-stream steps with an event pair around every map "
+                                  "call (%.3f ms/step)" % (args.steps, instrumented_ms),
             "bytes_per_cell": MAP_BYTES_PER_CELL,
             "algorithmic_bytes_per_launch": map_bytes_avg,
             "source_fingerprint": kernel_fingerprint(),

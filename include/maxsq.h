@@ -157,9 +157,10 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
 /*
  * Many matrices in one go.  h_mats is a host copy of the `count` descriptors whose device
  * copy is d_mats; results go to d_out[0 .. count-1] in the same order.  The tiles of all
- * matrices are spread over one grid-stride launch (the tile total is computed on the host from
- * h_mats and checked on the device against a prefix of d_mats' tile counts; a mismatch turns
- * every result into side -1 instead of running).  With the environment variable MAXSQ_GRAPH=1
+ * matrices are spread over one grid-stride launch.  The tile total and a fingerprint of every
+ * descriptor's (index, m, n, ld_words) are computed on the host from h_mats and checked on the
+ * device against d_mats; when the two copies disagree, every result is side -1 instead of a
+ * search (the Python binding raises).  With the environment variable MAXSQ_GRAPH=1
  * the launch sequence is captured once per (descriptors, shapes, output, workspace) into a HIP
  * graph and replayed on later calls.
  * The caller provides the workspace (size from ms_batched_workspace_size with the same

@@ -86,6 +86,13 @@ __device__ __forceinline__ int32_t uniform(int32_t v) {
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
 }
 
+// a / b for a >= 0, b > 0: one 32-bit division when both fit (every matrix dimension and tile
+// count short of 2^32), instead of the ~100-instruction 64-bit routine.
+__device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
+    if ((((uint64_t)a | (uint64_t)b) >> 32) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
+
 // Global index of the calling wave (uniform).
 __device__ __forceinline__ int64_t wave_index() {
     return uniform((int64_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE));
@@ -423,26 +430,38 @@ __device__ void serial_dp(const uint64_t *__restrict__ bits, int64_t m, int64_t 
 }
 
 // ----------------------------------------------------------------------------------------------
-// Erosion tile: 64 lanes = 16 word columns x 4 row groups; lane (rg, wl) holds RPL consecutive
-// rows of word wl.  Word column 0 is the left halo (its results are not owned); the first
-// KC - 1 rows of row group 0 are the top halo.  With that halo every E_k with k <= KC is exact
-// on the owned cells.
+// Erosion tile: 64 lanes = NWT word columns x NRG = 64 / NWT row groups; lane (rg, wl) holds RPL
+// consecutive rows of word wl.  Word column 0 is the left halo (its results are not owned); the
+// first KC - 1 rows of row group 0 are the top halo.  With that halo every E_k with k <= KC is
+// exact on the owned cells.  NWT = 16 is the wide tile (15 owned words, 64 / 128 rows); NWT = 4
+// suits matrices a few words wide (3 owned words, 16 row groups).
 // ----------------------------------------------------------------------------------------------
-template <int RPL_, int KC_>
+template <int RPL_, int KC_, int NWT_ = 16>
 struct TileShape {
     static constexpr int RPL = RPL_;
     static constexpr int KC = KC_;
-    static constexpr int NWT = 16;
-    static constexpr int NRG = 4;
+    static constexpr int NWT = NWT_;
+    static constexpr int NRG = WAVE / NWT;
     static constexpr int ROWS = NRG * RPL;
     static constexpr int HALO = KC - 1;
     static constexpr int TR = ROWS - HALO;  // owned rows per tile
     static constexpr int OWN_WORDS = NWT - 1;
+    static_assert(NWT == 4 || NWT == 8 || NWT == 16, "word columns per row group");
     static_assert(HALO < RPL, "top halo must fit in the first row group");
     static_assert(KC <= 32 && (KC & (KC - 1)) == 0, "KC power of two <= 32");
 };
 
-template <int RPL, int D>
+// Within each group of NWT lanes, lane l receives lane l-1's value; the first lane of every
+// group receives 0 (DPP row_shr:1, whose bound control zeroes the first lane of each 16-lane
+// row; narrower groups also clear their own first lane).
+template <int NWT>
+__device__ __forceinline__ uint32_t from_left_in_group(uint32_t v, int wl) {
+    const uint32_t x = from_left_in_row16(v);
+    if constexpr (NWT == 16) return x;
+    else return wl ? x : 0u;
+}
+
+template <int RPL, int D, int NWT>
 __device__ __forceinline__ void erode(const uint64_t (&E)[RPL], uint64_t (&T)[RPL], int rg,
                                       int wl) {
     static_assert(D >= 1 && D <= 16 && D <= RPL, "shift");
@@ -452,7 +471,7 @@ __device__ __forceinline__ void erode(const uint64_t (&E)[RPL], uint64_t (&T)[RP
         if (r >= D) {
             up = E[r - D];
         } else {
-            const uint64_t v = __shfl_up(E[RPL - D + r], 16);
+            const uint64_t v = __shfl_up(E[RPL - D + r], NWT);
             up = rg ? v : 0ull;
         }
         T[r] = E[r] & up;
@@ -460,21 +479,21 @@ __device__ __forceinline__ void erode(const uint64_t (&E)[RPL], uint64_t (&T)[RP
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const uint64_t f = T[r];
-        const uint32_t lh = from_left_in_row16((uint32_t)(f >> 32));
+        const uint32_t lh = from_left_in_group<NWT>((uint32_t)(f >> 32), wl);
         T[r] = f & ((f << D) | (uint64_t)(lh >> (32 - D)));
     }
 }
 
-template <int RPL>
+template <int RPL, int NWT>
 __device__ __forceinline__ void erode_by(const uint64_t (&E)[RPL], uint64_t (&T)[RPL], int d,
                                          int rg, int wl) {
     switch (d) {
-    case 1: erode<RPL, 1>(E, T, rg, wl); break;
-    case 2: erode<RPL, 2>(E, T, rg, wl); break;
-    case 4: erode<RPL, 4>(E, T, rg, wl); break;
-    case 8: erode<RPL, 8>(E, T, rg, wl); break;
+    case 1: erode<RPL, 1, NWT>(E, T, rg, wl); break;
+    case 2: erode<RPL, 2, NWT>(E, T, rg, wl); break;
+    case 4: erode<RPL, 4, NWT>(E, T, rg, wl); break;
+    case 8: erode<RPL, 8, NWT>(E, T, rg, wl); break;
     default:
-        if constexpr (RPL >= 16) erode<RPL, 16>(E, T, rg, wl);
+        if constexpr (RPL >= 16) erode<RPL, 16, NWT>(E, T, rg, wl);
         break;
     }
 }
@@ -571,7 +590,7 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
     ty = uniform(ty);
     tx = uniform(tx);
     const int lane = __lane_id();
-    const int wl = lane & 15, rg = lane >> 4;
+    const int wl = lane % TS::NWT, rg = lane / TS::NWT;
     const int64_t nwords = (n + 63) >> 6;
     const int64_t tile_r0 = ty * TS::TR - TS::HALO;
     const int64_t wlane = tx * TS::OWN_WORDS - 1 + wl;
@@ -597,47 +616,37 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
     const int64_t best = key_side(load_relaxed(sink.key));
     if (!any_owned<TS>(E, rg, lane_ok)) return 0;
 
-    // One loop, one erosion call site (each call site inlines the erosion bodies, and the
-    // register tile leaves little room): E holds E_cur, the step tries E_{cur + d} (d <= cur).
-    //   phase 0: doubling, d = cur, until E_{2 cur} is empty or cur reaches KC;
-    //   phase 1 (saturated): steps of DMAX rows while non-empty, inside the register tile, for a
-    //            lower bound past the halo (what lies above or left of the tile reads as zero,
-    //            so what survives is a subset of the true E_k: a real square);
-    //   phase 2: halving steps.  Unsaturated tiles stop as soon as their bracket cannot reach
-    //            the best side published so far.
+    // Two loops, two erosion call sites (each inlines the erosion bodies, and the register tile
+    // leaves little room).  E holds E_cur; a step tries E_{cur + d} with d <= cur.
+    //  * Growing: d = cur (doubling) up to KC; a tile reaching KC is saturated, and keeps growing
+    //    by DMAX rows inside its register tile for a lower bound past the halo (what lies above
+    //    or left of the tile reads as zero, so what survives is a subset of the true E_k: a real
+    //    square).
+    //  * Halving: d = (last step) / 2 down to 1.  Unsaturated tiles stop as soon as their bracket
+    //    cannot reach the best side published so far.
     constexpr int DMAX = TS::RPL < 16 ? TS::RPL : 16;
-    int cur = 1, d = 1, phase = 0;
+    int cur = 1;
     bool saturated = false;
     for (;;) {
-        erode_by<RPL>(E, T, d, rg, wl);
-        const bool ok = any_owned<TS>(T, rg, lane_ok);
-        if (ok) {
+        const int d = cur < TS::KC ? cur : DMAX;
+        if (saturated && cur + DMAX > TS::ROWS) break;
+        erode_by<RPL, TS::NWT>(E, T, d, rg, wl);
+        if (!any_owned<TS>(T, rg, lane_ok)) break;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) E[r] = T[r];
+        cur += d;
+        saturated = cur >= TS::KC;
+    }
+    // the tile's side is in [cur, 2 cur - 1] (unsaturated) or [cur, cur + DMAX - 1]
+    if (!saturated && 2 * cur - 1 < best) return 2 * cur - 1;
+    for (int d = saturated ? DMAX >> 1 : cur >> 1; d >= 1; d >>= 1) {
+        erode_by<RPL, TS::NWT>(E, T, d, rg, wl);
+        if (any_owned<TS>(T, rg, lane_ok)) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) E[r] = T[r];
             cur += d;
         }
-        if (phase == 0) {
-            if (!ok) {  // the tile's side is in [cur, 2 cur - 1]
-                if (2 * cur - 1 < best) return 2 * cur - 1;
-                phase = 2;
-                d = cur >> 1;
-            } else if (cur >= TS::KC) {
-                saturated = true;
-                phase = cur + DMAX <= TS::ROWS ? 1 : 2;
-                d = phase == 1 ? DMAX : DMAX >> 1;
-            } else {
-                d = cur;
-            }
-        } else if (phase == 1) {
-            if (!ok || cur + DMAX > TS::ROWS) {
-                phase = 2;
-                d = DMAX >> 1;
-            }
-        } else {
-            if (!saturated && cur + d - 1 < best) return cur + d - 1;
-            d >>= 1;
-        }
-        if (d == 0) break;
+        if (!saturated && cur + d - 1 < best) return cur + d - 1;
     }
     if (!saturated && cur < best) return cur;
     // first owned cell of E_cur in row-major order

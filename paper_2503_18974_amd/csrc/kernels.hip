@@ -13,8 +13,8 @@
 // and column windows that start S rows / columns early (zero state there is exact); after a
 // search in the same call, the halos follow each probe tile's bound.
 // Batched: k_batch_init (prefix of tile counts, clear keys), k_probe_batched (every tile of every
-// matrix in one grid-stride pass), k_batch_resolve (saturated tiles of every matrix),
-// k_batch_final (key -> result per matrix).
+// matrix in one grid-stride pass), k_batch_finish (the saturated tiles of every matrix if any,
+// then key -> result per matrix).
 #include <algorithm>
 #include <mutex>
 
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_probe(const uint64_t *__restrict__ bits
     sb.ntx = ntx;
     sb.stride = nwave;
     for (int64_t t = wave; t < ntiles; t += nwave) {
-        const int64_t ty = t / ntx, tx = t - ty * ntx;
+        const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
         sb.add(t, tile_search<TS>(bits, m, n, ldw, ty, tx, TileSink{&hdr->key}));
     }
     sb.flush();
@@ -313,21 +313,21 @@ __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_
     // wave's sequence of rows is the latency), a window one group narrower halves every row's
     // work, as long as it still leaves a 64-column output
     if (ng > 1 && (ng - 1) * GW >= hc + 64 &&
-        ((m + rmin - 1) / rmin) * ((n + ng * GW - hc - 1) / (ng * GW - hc)) < min_items)
+        udiv(m + rmin - 1, rmin) * udiv(n + ng * GW - hc - 1, ng * GW - hc) < min_items)
         ng -= 1;
     const int64_t ow = ng * GW - hc;
-    const int64_t nwin = (n + ow - 1) / ow;
+    const int64_t nwin = udiv(n + ow - 1, ow);
     // the tallest bands (the least halo work) that still leave min_items items
     int64_t R = band_rows > 4 * Sg ? band_rows : 4 * Sg;
-    while (R > rmin && ((m + R - 1) / R) * nwin < min_items) R = (R / 2 > rmin) ? R / 2 : rmin;
+    while (R > rmin && udiv(m + R - 1, R) * nwin < min_items) R = (R / 2 > rmin) ? R / 2 : rmin;
     // in region mode an item stays within 32 tile rows (one mask bit per tile row)
     if (region) R = R < 32 * tile_rows ? R : 32 * tile_rows;
     R = R < m ? R : m;
-    const int64_t items = ((m + R - 1) / R) * nwin;
+    const int64_t items = udiv(m + R - 1, R) * nwin;
     const int lane = __lane_id();
     Track dummy{0, 0};
     for (int64_t it = wave; it < items; it += nwave) {
-        const int64_t b = it / nwin, wdx = it - b * nwin;
+        const int64_t b = udiv(it, nwin), wdx = it - b * nwin;
         const int64_t ra = b * R, rb = ra + R < m ? ra + R : m;
         const int64_t rh = ra - Sg > 0 ? ra - Sg : 0;
         const int64_t xa = wdx * ow, xb = xa + ow < n ? xa + ow : n;
@@ -337,8 +337,8 @@ __device__ void narrow_pass(const uint64_t *__restrict__ bits, int64_t m, int64_
         if (region) {
             sc.on = true;
             sc.tile_rows = tile_rows;
-            sc.ty0 = ra / tile_rows;
-            const int64_t nk = (rb - 1) / tile_rows - sc.ty0 + 1;  // <= 33
+            sc.ty0 = udiv(ra, tile_rows);
+            const int64_t nk = udiv(rb - 1, tile_rows) - sc.ty0 + 1;  // <= 33
             bool any = false;
 #pragma unroll
             for (int g = 0; g < NGMAX; ++g) {
@@ -565,41 +565,80 @@ struct BatchCounters {
     uint32_t error;    // bit 1: the device prefix disagrees with the host's tile count
     uint32_t nsat;     // saturated tiles over the whole batch
     uint32_t nserial;  // matrices flagged for the serial pass
-    uint32_t pad[5];
+    uint32_t done;     // blocks of the finishing kernel done with their saturated tiles
+    uint32_t pad[4];
 };
 
-// One block: clear per-matrix keys and flags, exclusive prefix of tile counts.
+// The narrow tile of the batched path: 4 word columns (3 owned) x 16 row groups of 16 rows.
+// Matrices a few words wide leave most of a 16-word tile empty; per matrix, the batch takes
+// whichever tile does less erosion work (tiles x rows per lane, every tile being 64 lanes).
+// The same rule runs on the host (the tile total) and on the device (prefix, probe, resolve).
+using TSN = TileShape<16, 16, 4>;
+
 template <class TS>
-__device__ __forceinline__ uint64_t tiles_in(const ms_matrix &d) {
-    if (d.m <= 0 || d.n <= 0) return 0;
-    const int64_t nwords = (d.n + 63) >> 6;
-    return (uint64_t)(((d.m + TS::TR - 1) / TS::TR) *
-                      ((nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS));
+__host__ __device__ __forceinline__ int64_t tile_count(int64_t m, int64_t n) {
+    if (m <= 0 || n <= 0) return 0;
+    const int64_t nwords = (n + 63) >> 6;
+    return ((m + TS::TR - 1) / TS::TR) * ((nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS);
 }
 
+template <class TS>
+__host__ __device__ __forceinline__ bool narrow_tiles(int64_t m, int64_t n) {
+    return tile_count<TSN>(m, n) * TSN::RPL < tile_count<TS>(m, n) * TS::RPL;
+}
+
+// Tiles of one matrix of a batch whose wide tile is TS.
+template <class TS>
+__device__ __forceinline__ uint64_t tiles_in(const ms_matrix &d) {
+    return (uint64_t)(narrow_tiles<TS>(d.m, d.n) ? tile_count<TSN>(d.m, d.n)
+                                                  : tile_count<TS>(d.m, d.n));
+}
+
+// Fingerprint of a batch's shapes: the wrapping sum over i of a mix of (i, m, n, ld_words),
+// computed the same way on the host (from its copy of the descriptors) and on the device.
+__host__ __device__ __forceinline__ uint64_t shape_mix(uint64_t i, uint64_t m, uint64_t n,
+                                                       uint64_t ldw) {
+    uint64_t x = i * 0x9E3779B97F4A7C15ull ^ m * 0xC2B2AE3D27D4EB4Full ^
+                 n * 0x165667B19E3779F9ull ^ ldw * 0xD6E8FEB86659FD93ull;
+    x ^= x >> 31;  // splitmix64 finalizer
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 29;
+    x *= 0x94D049BB133111EBull;
+    return x ^ (x >> 32);
+}
+
+// One block: clear per-matrix keys and flags, exclusive prefix of tile counts.  When the device
+// descriptors' shapes do not match the host's fingerprint (the two copies differ), the total is
+// replaced by an impossible value, so the probe refuses the batch and every result reads -1.
 template <class TS>
 __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict__ mats,
                                                      int64_t count,
                                                      unsigned long long *__restrict__ keys,
                                                      uint64_t *__restrict__ prefix,
                                                      uint32_t *__restrict__ flags,
-                                                     BatchCounters *ctr) {
+                                                     BatchCounters *ctr, uint64_t host_mix) {
     __shared__ uint64_t part[1024];
+    __shared__ uint64_t mix[1024];
     const int tid = threadIdx.x;
     const int64_t per = (count + 1023) / 1024;
     const int64_t lo = tid * per, hi = lo + per < count ? lo + per : count;
-    uint64_t s = 0;
+    uint64_t s = 0, h = 0;
     for (int64_t i = lo; i < hi; ++i) {
         keys[i] = 0;
         flags[i] = 0;
-        s += tiles_in<TS>(mats[i]);
+        const ms_matrix d = mats[i];
+        s += tiles_in<TS>(d);
+        h += shape_mix((uint64_t)i, (uint64_t)d.m, (uint64_t)d.n, (uint64_t)d.ld_words);
     }
     part[tid] = s;
+    mix[tid] = h;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const uint64_t v = tid >= off ? part[tid - off] : 0;
+        const uint64_t w = tid >= off ? mix[tid - off] : 0;
         __syncthreads();
         part[tid] += v;
+        mix[tid] += w;
         __syncthreads();
     }
     uint64_t run = part[tid] - s;  // exclusive start of this thread's range
@@ -608,10 +647,11 @@ __global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict
         run += tiles_in<TS>(mats[i]);
     }
     if (tid == 1023) {
-        prefix[count] = part[1023];
+        prefix[count] = mix[1023] == host_mix ? part[1023] : ~0ull;
         ctr->error = 0;
         ctr->nsat = 0;
         ctr->nserial = 0;
+        ctr->done = 0;
     }
 }
 
@@ -648,29 +688,76 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
         const int64_t mi = find_matrix(prefix, count, item);
         const ms_matrix d = mats[mi];
         const int64_t nwords = (d.n + 63) >> 6;
-        const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
         const int64_t t = (int64_t)(item - prefix[mi]);
-        const int64_t ty = t / ntx, tx = t - ty * ntx;
-        sb.add((int64_t)item,
-               tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, TileSink{keys + mi}));
+        if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n))) {
+            const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
+            const int64_t ty = t / ntx, tx = t - ty * ntx;
+            sb.add((int64_t)item,
+                   tile_search<TSN>(d.bits, d.m, d.n, d.ld_words, ty, tx, TileSink{keys + mi}));
+        } else {
+            const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
+            const int64_t ty = t / ntx, tx = t - ty * ntx;
+            sb.add((int64_t)item,
+                   tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, TileSink{keys + mi}));
+        }
     }
     sb.flush();
     if (__lane_id() == 0 && sb.nsat) atomicAdd(&ctr->nsat, (uint32_t)sb.nsat);
 }
 
-// Saturated tiles of every matrix (none: every wave returns at once), spread over the waves.
-template <class TS>
-__global__ __launch_bounds__(256) void k_batch_resolve(const ms_matrix *__restrict__ mats,
-                                                       int64_t count,
-                                                       unsigned long long *__restrict__ keys,
-                                                       const uint64_t *__restrict__ prefix,
-                                                       uint32_t *__restrict__ flags,
-                                                       BatchCounters *ctr,
-                                                       const uint8_t *__restrict__ sat,
-                                                       uint64_t total) {
+// Key -> result of matrix i (the serial pass for a matrix flagged by the resolve pass, by the
+// calling wave, within the workspace's serial state).
+__device__ void batch_result(const ms_matrix *__restrict__ mats, int64_t i,
+                             const unsigned long long *__restrict__ keys,
+                             int32_t *serial_state, int64_t state_words, ms_square *out) {
+    const ms_matrix d = mats[i];
     const int lane = __lane_id();
-    if (uniform((int32_t)load_relaxed_u32(&ctr->nsat)) == 0) return;
-    if (load_relaxed_u32(&ctr->error)) return;
+    const int64_t nwords = (d.n + 63) >> 6;
+    if (uniform(nwords) > state_words) {  // wider than the state the workspace holds
+        if (lane == 0) out[i] = ms_square{-1, -1, -1};
+        return;
+    }
+    Track tr{0, INT64_MAX};
+    serial_dp<false>(d.bits, d.m, d.n, d.ld_words, nullptr, 0, serial_state,
+                     serial_state + nwords * 64, tr);
+    const Track w = wave_track(tr);
+    const unsigned long long key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
+    if (lane == 0) write_result(key, d.n, out + i);
+    (void)keys;
+}
+
+// After the probe: the results of every matrix.
+//  * An inconsistent batch (the probe refused it): every result -1.
+//  * No saturated tile (the common case): the keys are final; the grid writes the results,
+//    one matrix per thread, at once.
+//  * Otherwise the waves finish the saturated tiles of every matrix (resolve_tile), blocks count
+//    themselves done (a completion count, nothing waits), and the last block writes every
+//    result; its first wave runs the serial pass for the matrices whose square was too wide for
+//    the resolve window.
+template <class TS>
+__global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restrict__ mats,
+                                                      int64_t count,
+                                                      unsigned long long *__restrict__ keys,
+                                                      const uint64_t *__restrict__ prefix,
+                                                      uint32_t *__restrict__ flags,
+                                                      BatchCounters *ctr,
+                                                      const uint8_t *__restrict__ sat,
+                                                      uint64_t total, int32_t *serial_state,
+                                                      int64_t state_words, ms_square *out) {
+    const int lane = __lane_id();
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    if (uniform((int32_t)load_relaxed_u32(&ctr->error)) & 2) {
+        for (int64_t i = tid; i < count; i += nthr) out[i] = ms_square{-1, -1, -1};
+        return;
+    }
+    if (uniform((int32_t)load_relaxed_u32(&ctr->nsat)) == 0) {
+        for (int64_t i = tid; i < count; i += nthr) {
+            const ms_matrix d = mats[i];
+            write_result(load_relaxed(keys + i), d.n, out + i);
+        }
+        return;
+    }
     const uint64_t wave = (uint64_t)wave_index();
     const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
     for (uint64_t base = wave; base < total; base += 64 * nwave) {
@@ -683,56 +770,43 @@ __global__ __launch_bounds__(256) void k_batch_resolve(const ms_matrix *__restri
             const int64_t mi = find_matrix(prefix, count, item);
             const ms_matrix d = mats[mi];
             const int64_t nwords = (d.n + 63) >> 6;
-            const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
             const int64_t t = (int64_t)(item - prefix[mi]);
-            const int64_t ty = t / ntx, tx = t - ty * ntx;
-            resolve_tile<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
-                             keys + mi, flags + mi, nullptr, 0, 1, &ctr->nserial);
+            if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n))) {
+                const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
+                const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
+                resolve_tile<TSN>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
+                                  keys + mi, flags + mi, nullptr, 0, 1, &ctr->nserial);
+            } else {
+                const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
+                const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
+                resolve_tile<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
+                                 keys + mi, flags + mi, nullptr, 0, 1, &ctr->nserial);
+            }
         }
     }
-}
-
-// Key -> result per matrix, one matrix per thread; matrices with a square too wide for the
-// windowed pass are finished by block 0 with the serial pass (it owns the state buffer), found
-// 64 at a time by a ballot, and only when the resolve pass flagged any.
-__global__ __launch_bounds__(64) void k_batch_final(const ms_matrix *__restrict__ mats,
-                                                    int64_t count,
-                                                    const unsigned long long *__restrict__ keys,
-                                                    const uint32_t *__restrict__ flags,
-                                                    const BatchCounters *ctr,
-                                                    int32_t *serial_state, ms_square *out) {
-    const int lane = __lane_id();
-    const int64_t stride = (int64_t)gridDim.x * WAVE;
-    if (load_relaxed_u32(&ctr->error) & 2u) {  // inconsistent batch: report every result failed
-        for (int64_t i = (int64_t)blockIdx.x * WAVE + lane; i < count; i += stride)
-            out[i] = ms_square{-1, -1, -1};
-        return;
-    }
-    for (int64_t i = (int64_t)blockIdx.x * WAVE + lane; i < count; i += stride) {
+    // the last block to finish writes every result
+    __threadfence();
+    __syncthreads();
+    __shared__ uint32_t s_last;
+    if (threadIdx.x == 0) s_last = atomicAdd(&ctr->done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
         const ms_matrix d = mats[i];
         const bool serial = d.m > 0 && d.n > 0 && load_relaxed_u32(flags + i);
         if (!serial) write_result(load_relaxed(keys + i), d.n, out + i);
     }
-    if (blockIdx.x != 0 || load_relaxed_u32(&ctr->nserial) == 0) return;
+    if (threadIdx.x >= WAVE || load_relaxed_u32(&ctr->nserial) == 0) return;
     for (int64_t b0 = 0; b0 < count; b0 += WAVE) {
         bool flagged = false;
         if (b0 + lane < count) {
             const ms_matrix d = mats[b0 + lane];
             flagged = d.m > 0 && d.n > 0 && load_relaxed_u32(flags + b0 + lane);
         }
-        uint64_t todo = __ballot(flagged);
-        while (todo) {
-            const int64_t i = b0 + __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            const ms_matrix d = mats[i];
-            const int64_t nw64 = ((d.n + 63) >> 6) * 64;
-            Track tr{0, INT64_MAX};
-            serial_dp<false>(d.bits, d.m, d.n, d.ld_words, nullptr, 0, serial_state,
-                             serial_state + nw64, tr);
-            const Track w = wave_track(tr);
-            const unsigned long long key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
-            if (lane == 0) write_result(key, d.n, out + i);
-        }
+        for (uint64_t todo = __ballot(flagged); todo; todo &= todo - 1)
+            batch_result(mats, b0 + __ffsll((long long)todo) - 1, keys, serial_state,
+                         state_words, out);
     }
 }
 
@@ -1080,11 +1154,11 @@ hipError_t launch_max_square_noalloc(const LaunchEnv &env, int device, int varia
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Tiles of one matrix of a batch whose wide tile is TS (the device's rule, msk::tiles_in).
 template <class TS>
 static uint64_t tiles_of(const ms_matrix &d) {
-    if (d.m <= 0 || d.n <= 0) return 0;
-    const int64_t nwords = cdiv(d.n, 64);
-    return (uint64_t)(cdiv(d.m, TS::TR) * cdiv(nwords, TS::OWN_WORDS));
+    return (uint64_t)(msk::narrow_tiles<TS>(d.m, d.n) ? msk::tile_count<msk::TSN>(d.m, d.n)
+                                                       : msk::tile_count<TS>(d.m, d.n));
 }
 
 BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
@@ -1101,6 +1175,11 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
     }
     L.total_tiles = tiles;
     L.max_nwords = maxw;
+    uint64_t mix = 0;
+    for (int64_t i = 0; i < count; ++i)
+        mix += msk::shape_mix((uint64_t)i, (uint64_t)h_mats[i].m, (uint64_t)h_mats[i].n,
+                              (uint64_t)h_mats[i].ld_words);
+    L.shape_mix = mix;
     size_t off = 0;
     L.counters = off; off = align256(off + sizeof(msk::BatchCounters));
     L.keys = off; off = align256(off + sizeof(unsigned long long) * (size_t)count);
@@ -1122,7 +1201,7 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     auto *state = reinterpret_cast<int32_t *>(ws + L.serial_state);
     auto *sat = reinterpret_cast<uint8_t *>(ws + L.sat);
     hipLaunchKernelGGL(msk::k_batch_init<TS>, dim3(1), dim3(1024), 0, env.stream, mats, count,
-                       keys, prefix, flags, ctr);
+                       keys, prefix, flags, ctr, L.shape_mix);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t pblocks = std::max<int64_t>(
@@ -1130,16 +1209,13 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)pblocks), dim3(256), 0,
                        env.stream, mats, count, keys, prefix, ctr, sat, (uint64_t)L.total_tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t rblocks = std::max<int64_t>(
-        1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 8), (int64_t)env.num_cus * 2));
-    hipLaunchKernelGGL(msk::k_batch_resolve<TS>, dim3((unsigned)rblocks), dim3(256), 0,
+    // results, and the saturated tiles first if any (one launch)
+    const int64_t fblocks = std::max<int64_t>(
+        1, std::min<int64_t>(std::max<int64_t>(cdiv((int64_t)L.total_tiles, 8), cdiv(count, 256)),
+                             (int64_t)env.num_cus * 2));
+    hipLaunchKernelGGL(msk::k_batch_finish<TS>, dim3((unsigned)fblocks), dim3(256), 0,
                        env.stream, mats, count, keys, prefix, flags, ctr, sat,
-                       (uint64_t)L.total_tiles);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t fb = std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 64),
-                                                               (int64_t)env.num_cus * 4));
-    hipLaunchKernelGGL(msk::k_batch_final, dim3((unsigned)fb), dim3(64), 0, env.stream, mats,
-                       count, keys, flags, ctr, state, out);
+                       (uint64_t)L.total_tiles, state, L.max_nwords, out);
     return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ struct BatchLayout {
     size_t keys, prefix, counters, serial_state, flags, sat, total;
     uint64_t total_tiles;
     int64_t max_nwords;
+    uint64_t shape_mix;  // fingerprint of every (i, m, n, ld_words), checked on the device
 };
 BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count);
 hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_mats,

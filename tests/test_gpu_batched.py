@@ -145,3 +145,33 @@ def test_batched_graph_same_buffers_new_shapes(dev, monkeypatch):
             assert rc == 0
             got = [tuple(r) for r in out.cpu().tolist()]
             assert got == [oracle.max_square(a) for a in sets[k]], (rep, k)
+
+
+def test_mismatched_device_descriptors_fail_every_result(dev):
+    """The host and device copies of the descriptors list the same two matrices in a different
+    order: the tile total agrees, the shapes per index do not.  The device must refuse the batch
+    (every result -1) rather than search with the host's workspace layout."""
+    import ctypes
+    import torch
+    announce("batched mismatched descriptors")
+    a = W.gen_bernoulli(100, 200, 0.6, 21)
+    b = W.gen_bernoulli(200, 100, 0.6, 22)
+    da, db = to_dev_bits(oracle.pack(a), dev), to_dev_bits(oracle.pack(b), dev)
+    ma = M._Matrix(da.data_ptr(), 100, 200, da.stride(0))
+    mb = M._Matrix(db.data_ptr(), 200, 100, db.stride(0))
+    h_mats = (M._Matrix * 2)(ma, mb)
+    swapped = (M._Matrix * 2)(mb, ma)
+    d_mats = torch.frombuffer(bytearray(bytes(swapped)), dtype=torch.uint8).to(dev)
+    nbytes = M.ms_batched_workspace_size(None, h_mats, 2)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = torch.zeros((2, 3), dtype=torch.int64, device=dev)
+    st = M.ms_max_square_batched(None, h_mats, d_mats.data_ptr(), 2, out.data_ptr(),
+                                 ws.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    assert out.cpu().tolist() == [[-1, -1, -1], [-1, -1, -1]]
+    # the same call with matching copies is answered normally
+    d_ok = torch.frombuffer(bytearray(bytes(h_mats)), dtype=torch.uint8).to(dev)
+    st = M.ms_max_square_batched(None, h_mats, d_ok.data_ptr(), 2, out.data_ptr(),
+                                 ws.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    assert [tuple(r) for r in out.cpu().tolist()] == [oracle.max_square(a), oracle.max_square(b)]
