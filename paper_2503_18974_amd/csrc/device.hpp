@@ -510,6 +510,39 @@ __device__ __forceinline__ bool any_owned(const uint64_t (&T)[TS::RPL], int rg, 
     return __ballot(lane_ok && acc != 0) != 0;
 }
 
+// The deep rows of a tile: owned rows at least KC below its first owned row, i.e. register rows
+// >= 2 KC - 1.  Erosion inside the register tile treats what lies above it as zero, so a row
+// there is exact for every side up to 2 KC (2 KC - 1 rows above it are in the tile, and an
+// owned word has a whole word to its left).
+template <class TS>
+struct DeepRows {
+    static constexpr int FIRST = 2 * TS::KC - 1;
+    static constexpr int RG = FIRST / TS::RPL;  // the row group where they start
+    static constexpr int R = FIRST % TS::RPL;   // and the row there
+    static_assert(FIRST < TS::ROWS, "deep rows inside the register tile");
+};
+
+// any_owned over the owned cells (deep = false) or over the deep rows only.
+template <class TS>
+__device__ __forceinline__ bool any_in(const uint64_t (&T)[TS::RPL], int rg, bool lane_ok,
+                                       bool deep) {
+    using DR = DeepRows<TS>;
+    uint64_t a = 0, h = 0, t = 0;
+#pragma unroll
+    for (int r = 0; r < TS::RPL; ++r) {
+        if (r < TS::HALO) h |= T[r];
+        else a |= T[r];
+        if constexpr (DR::R != TS::HALO) {
+            if (r >= DR::R) t |= T[r];
+        }
+    }
+    if constexpr (DR::R == TS::HALO) t = a;
+    // every row of the lane past row group thr counts, and in group thr the rows from the split
+    const int thr = deep ? DR::RG : 0;
+    const uint64_t acc = rg > thr ? (a | h) : (rg == thr ? (deep ? t : a) : 0ull);
+    return __ballot(lane_ok && acc != 0) != 0;
+}
+
 // Where the outcome of one tile goes.
 struct TileSink {
     unsigned long long *key;   // atomicMax target: (side, first position) of the best square
@@ -517,10 +550,27 @@ struct TileSink {
 
 // Per-tile outcome of the probe for the tiles a wave visits (tile t0 + k * stride, k < 64):
 // the saturation byte (read by the resolve pass) and, when `bounds` is set, an upper bound on
-// the tile's largest side (read by the dp map; -1 for a saturated tile, which the resolve pass
-// replaces).  Written with one store per array per 64 tiles: a store per tile would make the
-// next tile's loads wait for it.
+// the tile's largest side (read by the dp map; negative for a saturated tile until the resolve
+// pass records its bound).  Written with one store per array per 64 tiles: a store per tile
+// would make the next tile's loads wait for it.
+//
+// Saturated tiles come in two kinds.  SAT_FULL: the resolve pass finishes every owned row.
+// SAT_TOP: the probe finished the deep rows exactly, and the resolve pass finishes the first KC
+// owned rows only.  tile_search returns SAT_BOUND for the first kind and top_code(b) for the
+// second, b being the deep rows' largest side (0 when it is below KC, where the first rows,
+// which reach KC, decide).  The saturation byte is 0 (not saturated), SAT_FULL or SAT_TOP; the
+// bounds array holds the code until the resolve pass replaces it with the tile's bound.
 constexpr int32_t SAT_BOUND = -1;
+constexpr uint8_t SAT_FULL = 1, SAT_TOP = 2;
+__host__ __device__ __forceinline__ int32_t top_code(int32_t b) { return -2 - b; }
+// The deep rows' side kept in a bounds entry (0 unless the entry is a top_code).
+__host__ __device__ __forceinline__ int32_t deep_side(int32_t code) {
+    return code < -1 ? -2 - code : 0;
+}
+// The saturation byte of a probe return.
+__host__ __device__ __forceinline__ uint8_t sat_byte(int32_t code) {
+    return code >= 0 ? 0 : (code == SAT_BOUND ? SAT_FULL : SAT_TOP);
+}
 // Largest side the dp map's narrow pass (512-column windows) covers.
 constexpr int32_t MAP_NARROW_REACH = 448;
 // When a square exceeds that reach, the map is split by tile: tiles bounded by REGION_SMALL are
@@ -537,22 +587,19 @@ struct SatBatch {
     int64_t ntx = 1;           // tiles per tile row (for the box)
     uint32_t box[4] = {0, 0, 0, 0};  // the wave's box so far (wave-uniform; BOX_LOW encoding)
     int64_t t0 = 0, stride = 1;
-    uint64_t bits = 0;
     int count = 0, nsat = 0;
-    int32_t mine = 0;  // lane k: the bound of the k-th collected tile
+    int32_t mine = 0;  // lane k: the probe's return for the k-th collected tile
     __device__ void add(int64_t t, int32_t bound) {
         const int32_t bu = uniform(bound);   // wave-uniform: keep the state in SGPRs
-        const int32_t su = bu < 0 ? 1 : 0;
         if (count == 0) t0 = uniform(t);
-        bits |= (uint64_t)su << count;
-        nsat += su;
+        nsat += bu < 0 ? 1 : 0;
         if (__lane_id() == count) mine = bu;
         if (++count == 64) flush();
     }
     __device__ void flush() {
         const int lane = __lane_id();
         if (lane < count) {
-            base[t0 + lane * stride] = (uint8_t)((bits >> lane) & 1);
+            base[t0 + lane * stride] = sat_byte(mine);
             if (bounds) bounds[t0 + lane * stride] = mine;
         }
         const bool big = want_box && lane < count && (mine < 0 || mine > REGION_SMALL);
@@ -567,20 +614,24 @@ struct SatBatch {
 #pragma unroll
             for (int k = 0; k < 4; ++k) box[k] = e[k] > box[k] ? e[k] : box[k];
         }
-        bits = 0;
         count = 0;
     }
 };
 
 // Search one tile: the largest k <= KC with an owned k x k all-ones square (exact), pushed as a
 // key with the first owned cell of E_k.  Returns an upper bound on the tile's largest side (exact
-// unless the search stopped early because the tile could not reach the best side so far), or
-// SAT_BOUND when E_KC is non-empty among the owned cells ("saturated": the resolve pass finishes
-// such a tile).  A saturated tile pushes a lower bound instead: the largest k whose erosion,
-// continued past the halo inside the register tile, still holds an owned cell.  Its corner is a
-// real cell with dp >= k; the exact pass later pushes the true first cell, which wins the key
-// (same side, smaller position) or a larger side.
-template <class TS>
+// unless the search stopped early because the tile could not reach the best side so far), or a
+// negative code when E_KC is non-empty among the owned cells ("saturated": the resolve pass
+// finishes such a tile).  A saturated tile goes on eroding inside its register tile, over its
+// deep rows only (exact there up to 2 KC): when they hold no E_2KC cell, their largest side and
+// its first cell are exact and pushed, and the tile is of kind SAT_TOP; otherwise it is SAT_FULL
+// and pushes (2 KC, the first deep cell of E_2KC), a real square.  Either push is later beaten
+// or matched by the exact pass over the remaining rows when those hold a larger side or the same
+// side earlier (the key keeps the larger side, then the smaller position).
+// With DEEP = false a saturated tile is always SAT_FULL and pushes a lower bound instead: the
+// largest k whose erosion, continued inside the register tile past its halo, still holds an
+// owned cell (a subset of the true E_k: a real square).
+template <class TS, bool DEEP = true>
 __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int64_t ty, int64_t tx, const TileSink &sink) {
     constexpr int RPL = TS::RPL;
@@ -618,50 +669,60 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
 
     // Two loops, two erosion call sites (each inlines the erosion bodies, and the register tile
     // leaves little room).  E holds E_cur; a step tries E_{cur + d} with d <= cur.
-    //  * Growing: d = cur (doubling) up to KC; a tile reaching KC is saturated, and keeps growing
-    //    by DMAX rows inside its register tile for a lower bound past the halo (what lies above
-    //    or left of the tile reads as zero, so what survives is a subset of the true E_k: a real
-    //    square).
+    //  * Growing: d = cur (doubling) up to KC; a tile reaching KC is saturated and goes on over
+    //    its deep rows by DSTEP rows a step, up to 2 KC.
     //  * Halving: d = (last step) / 2 down to 1.  Unsaturated tiles stop as soon as their bracket
     //    cannot reach the best side published so far.
     constexpr int DMAX = TS::RPL < 16 ? TS::RPL : 16;
+    constexpr int DSTEP = DMAX < TS::KC ? DMAX : TS::KC;  // divides KC: the steps end at 2 KC
+    constexpr int DEEP_MAX = 2 * TS::KC;
     int cur = 1;
     bool saturated = false;
     for (;;) {
-        const int d = cur < TS::KC ? cur : DMAX;
-        if (saturated && cur + DMAX > TS::ROWS) break;
+        const int d = cur < TS::KC ? cur : (DEEP ? DSTEP : DMAX);
+        if (DEEP ? (saturated && cur + d > DEEP_MAX) : (saturated && cur + DMAX > TS::ROWS)) break;
         erode_by<RPL, TS::NWT>(E, T, d, rg, wl);
-        if (!any_owned<TS>(T, rg, lane_ok)) break;
+        if (DEEP ? !any_in<TS>(T, rg, lane_ok, saturated) : !any_owned<TS>(T, rg, lane_ok)) break;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) E[r] = T[r];
         cur += d;
-        saturated = cur >= TS::KC;
+        if (!saturated && cur >= TS::KC) {
+            saturated = true;
+            // no deep row reaches KC: the first KC owned rows, which do, decide the tile
+            if (DEEP && !any_in<TS>(E, rg, lane_ok, true)) return top_code(0);
+        }
     }
-    // the tile's side is in [cur, 2 cur - 1] (unsaturated) or [cur, cur + DMAX - 1]
+    const bool full = saturated && (!DEEP || cur >= DEEP_MAX);
+    // the side (over the deep rows when saturated) is in [cur, 2 cur - 1] (unsaturated), in
+    // [cur, cur + DSTEP - 1] (saturated), or at least 2 KC (full)
     if (!saturated && 2 * cur - 1 < best) return 2 * cur - 1;
-    for (int d = saturated ? DMAX >> 1 : cur >> 1; d >= 1; d >>= 1) {
+    const int d0 = DEEP ? (full ? 0 : DSTEP >> 1) : DMAX >> 1;
+    for (int d = saturated ? d0 : cur >> 1; d >= 1; d >>= 1) {
         erode_by<RPL, TS::NWT>(E, T, d, rg, wl);
-        if (any_owned<TS>(T, rg, lane_ok)) {
+        if (DEEP ? any_in<TS>(T, rg, lane_ok, saturated) : any_owned<TS>(T, rg, lane_ok)) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) E[r] = T[r];
             cur += d;
         }
         if (!saturated && cur + d - 1 < best) return cur + d - 1;
     }
-    if (!saturated && cur < best) return cur;
-    // first owned cell of E_cur in row-major order
+    const int32_t ret = saturated ? (full ? SAT_BOUND : top_code(cur)) : cur;
+    if (DEEP ? cur < best : !saturated && cur < best) return ret;
+    // first owned (saturated: deep) cell of E_cur in row-major order
     int64_t pos = INT64_MAX;
     if (lane_ok) {
 #pragma unroll
         for (int r = RPL - 1; r >= 0; --r) {
-            const bool owned = rg || r >= TS::HALO;
+            using DR = DeepRows<TS>;
+            const bool take = DEEP && saturated ? (rg > DR::RG || (r >= DR::R && rg == DR::RG))
+                                                : (rg || r >= TS::HALO);
             const int64_t row = tile_r0 + rg * RPL + r;
-            if (owned && E[r]) pos = row * n + wlane * 64 + (__ffsll((long long)E[r]) - 1);
+            if (take && E[r]) pos = row * n + wlane * 64 + (__ffsll((long long)E[r]) - 1);
         }
     }
     pos = wave_min_i64(pos);
     if (lane == 0) atomicMax(sink.key, make_key(cur, pos));
-    return saturated ? SAT_BOUND : cur;
+    return ret;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -686,6 +747,10 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
 // (dp[i][j] <= dp[i-1][j] + 1), so the tile's first row gets a gallop-and-bisect search over k
 // and each later row a single test of k = best + 1.  The first row reaching the final best, and
 // its first column there, give the tile's first corner in row-major order.
+//
+// Rows.  A SAT_TOP tile's deep rows were finished exactly by the probe (their side and first
+// cell are in the key already), so the pass covers its first KC owned rows only; the tile's
+// bound is the larger of the two parts.
 // ----------------------------------------------------------------------------------------------
 constexpr int HB = 12;  // bit planes of H: heights up to 4095 (U + TR stays below)
 
@@ -901,9 +966,33 @@ __device__ bool resolve_pass(const uint64_t *__restrict__ bits, int64_t m, int64
 }
 
 // Records the tile's bound when the caller keeps bounds: the largest over the parts of the tile
-// (the probe left -1 there).
+// and, for a SAT_TOP tile, its deep rows (the probe left SAT_BOUND or a top_code there).
 __device__ __forceinline__ void note_bound(int32_t *bounds, int64_t t, int64_t bound) {
-    if (bounds && __lane_id() == 0) atomicMax(&bounds[t], (int32_t)bound);
+    if (bounds && __lane_id() == 0) {
+        const int32_t deep = deep_side(bounds[t]);
+        atomicMax(&bounds[t], (int32_t)(bound > deep ? bound : deep));
+    }
+}
+
+// The rows of a saturated tile left to the resolve pass: its first KC owned rows for a SAT_TOP
+// tile (the probe finished the rest), all TR otherwise.
+template <class TS>
+__device__ __forceinline__ int64_t resolve_rows(uint8_t sb) {
+    return sb == SAT_TOP ? TS::KC : TS::TR;
+}
+
+// The bound U of a saturated tile from the runs of saturated tiles (see above), at most
+// min(m, n).
+template <class TS>
+__device__ __forceinline__ int64_t resolve_bound(const uint8_t *__restrict__ sat, int64_t ty,
+                                                 int64_t tx, int64_t ntx, int64_t mn, int lane) {
+    constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
+    const int64_t t = ty * ntx + tx;
+    const int64_t vrun = uniform(sat_run(sat, t, ntx, ty + 1, lane));
+    const int64_t hrun = uniform(sat_run(sat, t, 1, tx + 1, lane));
+    const int64_t u =
+        (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
+    return u < mn ? u : mn;
 }
 
 // Finishes rows [ra + part * ceil(TR / nparts), ...) of a saturated tile: the tile's rows split
@@ -921,16 +1010,13 @@ __device__ void resolve_tile(const uint64_t *__restrict__ bits, int64_t m, int64
     ldw = uniform(ldw);
     ty = uniform(ty);
     tx = uniform(tx);
-    const int64_t prow = (TS::TR + nparts - 1) / nparts;
-    const int64_t ta = ty * TS::TR, tb = ta + TS::TR < m ? ta + TS::TR : m;
+    const int64_t rows = resolve_rows<TS>((uint8_t)uniform((int32_t)sat[ty * ntx + tx]));
+    const int64_t prow = (rows + nparts - 1) / nparts;
+    const int64_t ta = ty * TS::TR, tb = ta + rows < m ? ta + rows : m;
     const int64_t ra = ta + part * prow < tb ? ta + part * prow : tb;
     const int64_t rb = ra + prow < tb ? ra + prow : tb;
     if (ra >= rb) return;
-    const int64_t vrun = uniform(sat_run(sat, ty * ntx + tx, ntx, ty + 1, lane));
-    const int64_t hrun = uniform(sat_run(sat, ty * ntx + tx, 1, tx + 1, lane));
-    int64_t ucap = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
-    const int64_t mn = m < n ? m : n;
-    ucap = ucap < mn ? ucap : mn;
+    const int64_t ucap = resolve_bound<TS>(sat, ty, tx, ntx, m < n ? m : n, lane);
     const int64_t g = uniform(key_side(load_relaxed(key)));
     if (ucap < g) {  // cannot reach the best side found so far
         note_bound(bounds, ty * ntx + tx, ucap);
@@ -984,18 +1070,16 @@ __device__ uint32_t resolve_group(const uint64_t *__restrict__ bits, int64_t m, 
     ty = uniform(ty);
     tx0 = uniform(tx0);
     tx1 = uniform(tx1);
-    const int64_t ta = ty * TS::TR, tb = ta + TS::TR < m ? ta + TS::TR : m;
     const int64_t mn = m < n ? m : n;
     const int64_t g = uniform(key_side(load_relaxed(key)));
-    // members still in the running (bit k), and the largest of their bounds
+    // members still in the running (bit k), the largest of their bounds, and the rows the span
+    // covers (every member's rows)
     uint32_t live = 0;
-    int64_t lo = -1, hi = -1, ucap = 0;
+    int64_t lo = -1, hi = -1, ucap = 0, rows = 0;
     for (int64_t tx = tx0; tx <= tx1; ++tx) {
-        if (!uniform((int32_t)sat[ty * ntx + tx])) continue;
-        const int64_t vrun = uniform(sat_run(sat, ty * ntx + tx, ntx, ty + 1, lane));
-        const int64_t hrun = uniform(sat_run(sat, ty * ntx + tx, 1, tx + 1, lane));
-        int64_t u = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
-        u = u < mn ? u : mn;
+        const uint8_t sb = (uint8_t)uniform((int32_t)sat[ty * ntx + tx]);
+        if (!sb) continue;
+        const int64_t u = resolve_bound<TS>(sat, ty, tx, ntx, mn, lane);
         if (u < g) {  // cannot reach the best side found so far
             note_bound(bounds, ty * ntx + tx, u);
             continue;
@@ -1004,8 +1088,10 @@ __device__ uint32_t resolve_group(const uint64_t *__restrict__ bits, int64_t m, 
         if (lo < 0) lo = tx;
         hi = tx;
         ucap = u > ucap ? u : ucap;
+        rows = resolve_rows<TS>(sb) > rows ? resolve_rows<TS>(sb) : rows;
     }
     if (__popc(live) <= 1) return live;
+    const int64_t ta = ty * TS::TR, tb = ta + rows < m ? ta + rows : m;
     const auto fits = [&](int64_t U) {
         const int64_t w0 = lo * OWN_COLS - U > 0 ? ((lo * OWN_COLS - U) >> 6) : 0;
         const int64_t w1 = ((hi + 1) * OWN_COLS < n ? (hi + 1) * OWN_COLS + 63 : n + 63) >> 6;
@@ -1125,13 +1211,11 @@ __device__ void resolve_tile_block(const uint64_t *__restrict__ bits, int64_t m,
     ty = uniform(ty);
     tx = uniform(tx);
     const int64_t t = ty * ntx + tx;
-    const int64_t ta = ty * TS::TR, tb = ta + TS::TR < m ? ta + TS::TR : m;
+    const int64_t rows = resolve_rows<TS>((uint8_t)uniform((int32_t)sat[t]));
+    const int64_t ta = ty * TS::TR, tb = ta + rows < m ? ta + rows : m;
     const int64_t mn = m < n ? m : n;
     if (wv == 0) {
-        const int64_t vrun = uniform(sat_run(sat, t, ntx, ty + 1, lane));
-        const int64_t hrun = uniform(sat_run(sat, t, 1, tx + 1, lane));
-        int64_t u = (vrun * TS::TR < hrun * OWN_COLS ? vrun * TS::TR : hrun * OWN_COLS) + TS::KC - 1;
-        u = u < mn ? u : mn;
+        const int64_t u = resolve_bound<TS>(sat, ty, tx, ntx, mn, lane);
         const int64_t g0 = uniform(key_side(load_relaxed(key)));
         if (lane == 0) {
             L.scal[0] = u;
@@ -1154,7 +1238,7 @@ __device__ void resolve_tile_block(const uint64_t *__restrict__ bits, int64_t m,
     // one pass at the bound when its window fits (exact at once), else doubling from twice the
     // best side so far
     int64_t U = fits(ucap) ? ucap : 2 * (g > TS::KC ? g : TS::KC);
-    const int64_t prow = (TS::TR + NW - 1) / NW;
+    const int64_t prow = (rows + NW - 1) / NW;
     const int64_t ra = uniform(ta + wv * prow < tb ? ta + wv * prow : tb);
     const int64_t rb = uniform(ra + prow < tb ? ra + prow : tb);
     const int64_t nwords = (n + 63) >> 6;

@@ -12,9 +12,9 @@
 // dp map (one more launch): k_dpmap reads S on the device and covers the matrix with row bands
 // and column windows that start S rows / columns early (zero state there is exact); after a
 // search in the same call, the halos follow each probe tile's bound.
-// Batched: k_batch_init (prefix of tile counts, clear keys), k_probe_batched (every tile of every
-// matrix in one grid-stride pass), k_batch_finish (the saturated tiles of every matrix if any,
-// then key -> result per matrix).
+// Batched: k_batch_count and k_batch_offsets (tile starts, clear keys, check the descriptors),
+// k_probe_batched (every tile of every matrix in one grid-stride pass), k_batch_finish (the
+// saturated tiles of every matrix if any, then key -> result per matrix).
 #include <algorithm>
 #include <mutex>
 
@@ -562,7 +562,7 @@ __global__ void k_clear_header(mshost::ScratchHeader *hdr) {
 
 // ---------------------------------------------------------------------------------- batched
 struct BatchCounters {
-    uint32_t error;    // bit 1: the device prefix disagrees with the host's tile count
+    uint32_t error;    // bit 1: the device tile total disagrees with the host's
     uint32_t nsat;     // saturated tiles over the whole batch
     uint32_t nserial;  // matrices flagged for the serial pass
     uint32_t done;     // blocks of the finishing kernel done with their saturated tiles
@@ -572,7 +572,7 @@ struct BatchCounters {
 // The narrow tile of the batched path: 4 word columns (3 owned) x 16 row groups of 16 rows.
 // Matrices a few words wide leave most of a 16-word tile empty; per matrix, the batch takes
 // whichever tile does less erosion work (tiles x rows per lane, every tile being 64 lanes).
-// The same rule runs on the host (the tile total) and on the device (prefix, probe, resolve).
+// The same rule runs on the host (the tile total) and on the device (tile starts, probe, resolve).
 using TSN = TileShape<16, 16, 4>;
 
 template <class TS>
@@ -607,76 +607,146 @@ __host__ __device__ __forceinline__ uint64_t shape_mix(uint64_t i, uint64_t m, u
     return x ^ (x >> 32);
 }
 
-// One block: clear per-matrix keys and flags, exclusive prefix of tile counts.  When the device
-// descriptors' shapes do not match the host's fingerprint (the two copies differ), the total is
-// replaced by an impossible value, so the probe refuses the batch and every result reads -1.
+// Where each matrix's tiles start in the batch's tile numbering, kept in two levels: the
+// matrices are cut into init blocks of INIT_BLOCK; local[i] is the start of matrix i within its
+// block and off[b] the start of block b (off[nblk] the total, or ~0 when the device
+// descriptors disagree with the host's fingerprint).
+constexpr int INIT_BLOCK = 256;
+
+struct BatchIndex {
+    const uint64_t *local;
+    const uint64_t *off;
+    int64_t count, nblk;
+    __device__ uint64_t start(int64_t i) const { return off[i / INIT_BLOCK] + local[i]; }
+    // The matrix holding tile `item` (< the total): the last matrix whose start is <= item
+    // (matrices without tiles share the next one's start and are skipped).
+    __device__ int64_t find(uint64_t item) const {
+        int64_t lo = 0, hi = nblk;  // off[lo] <= item < off[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (off[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t rel = item - off[lo];
+        int64_t a = lo * INIT_BLOCK;
+        int64_t c = a + INIT_BLOCK < count ? a + INIT_BLOCK : count;  // local[a] <= rel
+        while (c - a > 1) {
+            const int64_t mid = (a + c) >> 1;
+            if (local[mid] <= rel) a = mid;
+            else c = mid;
+        }
+        return a;
+    }
+};
+
+struct InitPart {
+    uint64_t tiles, mix;  // an init block's tile count and wrapping sum of shape_mix
+};
+
+// Batch setup, first pass: one matrix per thread, INIT_BLOCK per block.  Clears the matrix's
+// key and flag, writes its tile start within the block (an exclusive scan of tiles_in) and the
+// block's totals; block 0 clears the counters.
 template <class TS>
-__global__ __launch_bounds__(1024) void k_batch_init(const ms_matrix *__restrict__ mats,
-                                                     int64_t count,
-                                                     unsigned long long *__restrict__ keys,
-                                                     uint64_t *__restrict__ prefix,
-                                                     uint32_t *__restrict__ flags,
-                                                     BatchCounters *ctr, uint64_t host_mix) {
-    __shared__ uint64_t part[1024];
-    __shared__ uint64_t mix[1024];
-    const int tid = threadIdx.x;
-    const int64_t per = (count + 1023) / 1024;
-    const int64_t lo = tid * per, hi = lo + per < count ? lo + per : count;
-    uint64_t s = 0, h = 0;
-    for (int64_t i = lo; i < hi; ++i) {
+__global__ __launch_bounds__(INIT_BLOCK) void k_batch_count(const ms_matrix *__restrict__ mats,
+                                                            int64_t count,
+                                                            unsigned long long *__restrict__ keys,
+                                                            uint64_t *__restrict__ local,
+                                                            uint32_t *__restrict__ flags,
+                                                            InitPart *__restrict__ parts,
+                                                            BatchCounters *ctr) {
+    constexpr int NW = INIT_BLOCK / WAVE;
+    __shared__ uint64_t wt[NW], wm[NW];
+    const int lane = __lane_id(), wv = threadIdx.x / WAVE;
+    const int64_t i = (int64_t)blockIdx.x * INIT_BLOCK + threadIdx.x;
+    uint64_t t = 0, h = 0;
+    if (i < count) {
+        const ms_matrix d = mats[i];
         keys[i] = 0;
         flags[i] = 0;
-        const ms_matrix d = mats[i];
-        s += tiles_in<TS>(d);
-        h += shape_mix((uint64_t)i, (uint64_t)d.m, (uint64_t)d.n, (uint64_t)d.ld_words);
+        t = tiles_in<TS>(d);
+        h = shape_mix((uint64_t)i, (uint64_t)d.m, (uint64_t)d.n, (uint64_t)d.ld_words);
     }
-    part[tid] = s;
-    mix[tid] = h;
+    uint64_t incl = t, hs = h;  // inclusive scan of t and sum of h over the wave
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint64_t v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+        hs += __shfl_xor(hs, o);
+    }
+    if (lane == WAVE - 1) wt[wv] = incl;
+    if (lane == 0) wm[wv] = hs;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint64_t v = tid >= off ? part[tid - off] : 0;
-        const uint64_t w = tid >= off ? mix[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        mix[tid] += w;
-        __syncthreads();
+    uint64_t before = 0, tot = 0, mtot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        before += w < wv ? wt[w] : 0;
+        tot += wt[w];
+        mtot += wm[w];
     }
-    uint64_t run = part[tid] - s;  // exclusive start of this thread's range
-    for (int64_t i = lo; i < hi; ++i) {
-        prefix[i] = run;
-        run += tiles_in<TS>(mats[i]);
-    }
-    if (tid == 1023) {
-        prefix[count] = mix[1023] == host_mix ? part[1023] : ~0ull;
-        ctr->error = 0;
-        ctr->nsat = 0;
-        ctr->nserial = 0;
-        ctr->done = 0;
+    if (i < count) local[i] = before + incl - t;
+    if (threadIdx.x == 0) {
+        parts[blockIdx.x] = InitPart{tot, mtot};
+        if (blockIdx.x == 0) {
+            ctr->error = 0;
+            ctr->nsat = 0;
+            ctr->nserial = 0;
+            ctr->done = 0;
+        }
     }
 }
 
-__device__ __forceinline__ int64_t find_matrix(const uint64_t *__restrict__ prefix, int64_t count,
-                                               uint64_t item) {
-    int64_t lo = 0, hi = count;  // prefix[lo] <= item < prefix[hi]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (prefix[mid] <= item) lo = mid;
-        else hi = mid;
+// Batch setup, second pass (one block): off[b] = exclusive scan of the blocks' tile counts, and
+// off[nblk] = the total when the fingerprint of the device descriptors equals the host's, else
+// an impossible value, so the probe refuses the batch and every result reads -1.
+__global__ __launch_bounds__(1024) void k_batch_offsets(const InitPart *__restrict__ parts,
+                                                        int64_t nblk, uint64_t *__restrict__ off,
+                                                        uint64_t host_mix) {
+    constexpr int NT = 1024, NW = NT / WAVE;
+    __shared__ uint64_t wt[NW], wm[NW];
+    const int lane = __lane_id(), wv = threadIdx.x / WAVE;
+    uint64_t carry = 0, mix = 0;
+    for (int64_t c0 = 0; c0 < nblk; c0 += NT) {
+        const int64_t j = c0 + threadIdx.x;
+        const InitPart p = j < nblk ? parts[j] : InitPart{0, 0};
+        uint64_t incl = p.tiles, hs = p.mix;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint64_t v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+            hs += __shfl_xor(hs, o);
+        }
+        if (lane == WAVE - 1) wt[wv] = incl;
+        if (lane == 0) wm[wv] = hs;
+        __syncthreads();
+        uint64_t before = 0, tot = 0, mtot = 0;
+        for (int w = 0; w < NW; ++w) {
+            before += w < wv ? wt[w] : 0;
+            tot += wt[w];
+            mtot += wm[w];
+        }
+        if (j < nblk) off[j] = carry + before + incl - p.tiles;
+        carry += tot;
+        mix += mtot;
+        __syncthreads();  // wt and wm are rewritten by the next chunk
     }
-    return lo;
+    if (threadIdx.x == 0) off[nblk] = mix == host_mix ? carry : ~0ull;
 }
 
 // Tiles of all matrices in one grid-stride pass; the item count comes from the host (it is
 // computed from the same descriptors), so the loop is bounded by construction.  A mismatch with
-// the device-side prefix marks the whole batch as failed instead of running.
+// the device-side total marks the whole batch as failed instead of running.  The batched path
+// keeps the probe's plain saturated search (DEEP = false): its small matrices rarely saturate,
+// and the deep-row search made the common unsaturated tile slower.
 template <class TS>
 __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restrict__ mats,
-                                                       int64_t count,
                                                        unsigned long long *__restrict__ keys,
-                                                       const uint64_t *__restrict__ prefix,
+                                                       const uint64_t *__restrict__ local,
+                                                       const uint64_t *__restrict__ off,
+                                                       int64_t count, int64_t nblk,
                                                        BatchCounters *ctr,
                                                        uint8_t *__restrict__ sat, uint64_t total) {
-    if (__hip_atomic_load(prefix + count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != total) {
+    // the index arrays come in as restrict-qualified kernel arguments (nothing in the kernel
+    // writes them), so their wave-uniform reads can go through the scalar cache
+    const BatchIndex ix{local, off, count, nblk};
+    if (__hip_atomic_load(ix.off + ix.nblk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != total) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->error, 2u);
         return;
     }
@@ -685,20 +755,20 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
     SatBatch sb{sat};
     sb.stride = (int64_t)nwave;
     for (uint64_t item = wave; item < total; item += nwave) {
-        const int64_t mi = find_matrix(prefix, count, item);
+        const int64_t mi = ix.find(item);
         const ms_matrix d = mats[mi];
         const int64_t nwords = (d.n + 63) >> 6;
-        const int64_t t = (int64_t)(item - prefix[mi]);
+        const int64_t t = (int64_t)(item - ix.start(mi));
         if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n))) {
             const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
             const int64_t ty = t / ntx, tx = t - ty * ntx;
-            sb.add((int64_t)item,
-                   tile_search<TSN>(d.bits, d.m, d.n, d.ld_words, ty, tx, TileSink{keys + mi}));
+            sb.add((int64_t)item, tile_search<TSN, false>(d.bits, d.m, d.n, d.ld_words, ty, tx,
+                                                          TileSink{keys + mi}));
         } else {
             const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
             const int64_t ty = t / ntx, tx = t - ty * ntx;
-            sb.add((int64_t)item,
-                   tile_search<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, TileSink{keys + mi}));
+            sb.add((int64_t)item, tile_search<TS, false>(d.bits, d.m, d.n, d.ld_words, ty, tx,
+                                                         TileSink{keys + mi}));
         }
     }
     sb.flush();
@@ -736,15 +806,17 @@ __device__ void batch_result(const ms_matrix *__restrict__ mats, int64_t i,
 //    the resolve window.
 template <class TS>
 __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restrict__ mats,
-                                                      int64_t count,
                                                       unsigned long long *__restrict__ keys,
-                                                      const uint64_t *__restrict__ prefix,
+                                                      const uint64_t *__restrict__ local,
+                                                      const uint64_t *__restrict__ off,
+                                                      int64_t count, int64_t nblk,
                                                       uint32_t *__restrict__ flags,
                                                       BatchCounters *ctr,
                                                       const uint8_t *__restrict__ sat,
                                                       uint64_t total, int32_t *serial_state,
                                                       int64_t state_words, ms_square *out) {
     const int lane = __lane_id();
+    const BatchIndex ix{local, off, count, nblk};
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
     if (uniform((int32_t)load_relaxed_u32(&ctr->error)) & 2) {
@@ -767,19 +839,20 @@ __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restric
             const int l = __ffsll((long long)b) - 1;
             b &= b - 1;
             const uint64_t item = base + (uint64_t)l * nwave;
-            const int64_t mi = find_matrix(prefix, count, item);
+            const int64_t mi = ix.find(item);
             const ms_matrix d = mats[mi];
             const int64_t nwords = (d.n + 63) >> 6;
-            const int64_t t = (int64_t)(item - prefix[mi]);
+            const uint64_t st = ix.start(mi);
+            const int64_t t = (int64_t)(item - st);
             if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n))) {
                 const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
                 const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
-                resolve_tile<TSN>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
+                resolve_tile<TSN>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + st,
                                   keys + mi, flags + mi, nullptr, 0, 1, &ctr->nserial);
             } else {
                 const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
                 const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
-                resolve_tile<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + prefix[mi],
+                resolve_tile<TS>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + st,
                                  keys + mi, flags + mi, nullptr, 0, 1, &ctr->nserial);
             }
         }
@@ -1182,8 +1255,11 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
     L.shape_mix = mix;
     size_t off = 0;
     L.counters = off; off = align256(off + sizeof(msk::BatchCounters));
+    L.nblk = std::max<int64_t>(1, cdiv(count, msk::INIT_BLOCK));
     L.keys = off; off = align256(off + sizeof(unsigned long long) * (size_t)count);
-    L.prefix = off; off = align256(off + sizeof(uint64_t) * (size_t)(count + 1));
+    L.local = off; off = align256(off + sizeof(uint64_t) * (size_t)count);
+    L.parts = off; off = align256(off + sizeof(msk::InitPart) * (size_t)L.nblk);
+    L.offsets = off; off = align256(off + sizeof(uint64_t) * (size_t)(L.nblk + 1));
     L.flags = off; off = align256(off + sizeof(uint32_t) * (size_t)count);
     L.serial_state = off; off = align256(off + sizeof(int32_t) * 2 * 64 * (size_t)maxw);
     L.sat = off; off = align256(off + (size_t)tiles);
@@ -1196,25 +1272,33 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
                                    ms_square *out, char *ws, const BatchLayout &L) {
     auto *ctr = reinterpret_cast<msk::BatchCounters *>(ws + L.counters);
     auto *keys = reinterpret_cast<unsigned long long *>(ws + L.keys);
-    auto *prefix = reinterpret_cast<uint64_t *>(ws + L.prefix);
+    auto *local = reinterpret_cast<uint64_t *>(ws + L.local);
+    auto *parts = reinterpret_cast<msk::InitPart *>(ws + L.parts);
+    auto *offs = reinterpret_cast<uint64_t *>(ws + L.offsets);
     auto *flags = reinterpret_cast<uint32_t *>(ws + L.flags);
     auto *state = reinterpret_cast<int32_t *>(ws + L.serial_state);
     auto *sat = reinterpret_cast<uint8_t *>(ws + L.sat);
-    hipLaunchKernelGGL(msk::k_batch_init<TS>, dim3(1), dim3(1024), 0, env.stream, mats, count,
-                       keys, prefix, flags, ctr, L.shape_mix);
+    // setup: per-matrix tile starts within init blocks and the blocks' totals, then the blocks'
+    // starts and the fingerprint check
+    hipLaunchKernelGGL(msk::k_batch_count<TS>, dim3((unsigned)L.nblk), dim3(msk::INIT_BLOCK), 0,
+                       env.stream, mats, count, keys, local, flags, parts, ctr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(msk::k_batch_offsets, dim3(1), dim3(1024), 0, env.stream, parts, L.nblk,
+                       offs, L.shape_mix);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t pblocks = std::max<int64_t>(
         1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 4), (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)pblocks), dim3(256), 0,
-                       env.stream, mats, count, keys, prefix, ctr, sat, (uint64_t)L.total_tiles);
+                       env.stream, mats, keys, local, offs, count, L.nblk, ctr, sat,
+                       (uint64_t)L.total_tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // results, and the saturated tiles first if any (one launch)
     const int64_t fblocks = std::max<int64_t>(
         1, std::min<int64_t>(std::max<int64_t>(cdiv((int64_t)L.total_tiles, 8), cdiv(count, 256)),
                              (int64_t)env.num_cus * 2));
     hipLaunchKernelGGL(msk::k_batch_finish<TS>, dim3((unsigned)fblocks), dim3(256), 0,
-                       env.stream, mats, count, keys, prefix, flags, ctr, sat,
+                       env.stream, mats, keys, local, offs, count, L.nblk, flags, ctr, sat,
                        (uint64_t)L.total_tiles, state, L.max_nwords, out);
     return hipGetLastError();
 }

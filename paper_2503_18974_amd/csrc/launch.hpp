@@ -101,7 +101,10 @@ hipError_t launch_max_square_noalloc(const LaunchEnv &env, int device, int varia
 
 // Batched: workspace layout and launches.
 struct BatchLayout {
-    size_t keys, prefix, counters, serial_state, flags, sat, total;
+    // byte offsets in the workspace: per-matrix keys, tile starts within an init block, flags;
+    // per-init-block totals and starts; counters, serial-pass state, saturation bytes; the size
+    size_t keys, local, parts, offsets, counters, serial_state, flags, sat, total;
+    int64_t nblk;  // init blocks (at least one)
     uint64_t total_tiles;
     int64_t max_nwords;
     uint64_t shape_mix;  // fingerprint of every (i, m, n, ld_words), checked on the device

@@ -49,6 +49,32 @@ def test_batched_edges(dev):
     check_batch(mats, dev)
 
 
+def test_batched_many_blocks_with_empty_runs(dev):
+    """More matrices than one init block of 256: empty matrices at both ends of every block and
+    a whole block of empty matrices (its tile start equals the next block's), so the two-level
+    lookup of a tile's matrix meets equal starts within and across blocks."""
+    announce("batched 700, empty runs")
+    rng = np.random.default_rng(17)
+    mats = []
+    for k in range(700):
+        empty = k % 256 in (0, 1, 254, 255) or 256 <= k < 512 or k == 699
+        if empty:
+            mats.append(np.zeros((int(rng.integers(0, 3)), 0), np.uint8) if k % 2 else
+                        np.zeros((0, int(rng.integers(0, 40))), np.uint8))
+        else:
+            m, n = int(rng.integers(1, 90)), int(rng.integers(1, 200))
+            mats.append((rng.random((m, n)) < rng.uniform(0.3, 0.95)).astype(np.uint8))
+    items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
+    got = M.max_square_batched(items)
+    for a, g in zip(mats, got):
+        assert (g.side, g.row, g.col) == oracle.max_square(a), (a.shape, g)
+
+
+def test_batched_empty_batch(dev):
+    announce("batched count 0")
+    assert M.max_square_batched([]) == []
+
+
 def test_batched_large_square_serial_path(dev):
     """A square far beyond the erosion tile's certified side (the resolve pass bounds it by the
     runs of saturated tiles and takes it in one window of 33 words)."""

@@ -225,6 +225,60 @@ def test_equal_squares_first_corner(dev, layout):
     assert_same(a, dev)
 
 
+# Probe tiles per variant: (owned rows TR, certified side KC).  The owned rows of a tile at
+# offset >= KC from its first row (the "deep" rows) are exact inside the probe's register tile
+# for sides up to 2 KC; the resolve pass then finishes only the first KC rows of the tile.
+PROBE_TILES = {0: (49, 16), 1: (113, 16), 2: (97, 32)}
+
+
+def _deep_rows_cases(TR, KC):
+    """(name, [(bottom row offset in tile row 1, side)]): squares whose bottom-right corners sit
+    in the first KC rows or the deep rows of one tile, around every boundary that matters."""
+    last = TR - 1
+    return [
+        ("tie_top_last_vs_deep_first", [(KC - 1, KC + 3), (KC, KC + 3)]),
+        ("deep_larger", [(2, KC + 1), (last, 2 * KC - 1)]),
+        ("deep_full", [(3, KC + 2), (last, 2 * KC + 2)]),
+        ("top_only", [(KC - 1, KC + 4)]),
+        ("deep_exactly_2kc", [(0, 2 * KC - 1), (last, 2 * KC)]),
+        ("tie_2kc_minus_1", [(1, 2 * KC - 1), (KC + 1, 2 * KC - 1)]),
+        ("deep_reaches_tile_above", [(KC, 2 * KC - 1)]),
+        ("deep_2kc_from_register_row_0", [(KC, 2 * KC)]),
+        ("deep_past_register_tile", [(KC, 2 * KC + 1)]),
+        ("deep_below_kc_top_kc", [(KC - 2, KC), (KC + 5, KC - 1)]),
+        # first-row squares reaching deep into the tile above, whose last row then holds a
+        # square of side s - KC: below KC, between KC and 2 KC, and beyond 2 KC
+        ("first_rows_above_unsaturated", [(KC - 1, 2 * KC - 1)]),
+        ("first_rows_above_deep", [(KC - 1, 2 * KC + 5)]),
+        ("first_rows_above_full", [(KC - 1, 3 * KC + 2)]),
+    ]
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_deep_rows_of_saturated_tiles(dev, variant):
+    """Saturated tiles whose deep rows the probe finishes: ties between the first rows and the
+    deep rows, sides at 2 KC - 1, 2 KC and beyond, squares reaching into the tile above, a
+    tile whose deep rows stay below KC, and first-row squares reaching deep into the tile
+    above."""
+    TR, KC = PROBE_TILES[variant]
+    ctx = M.Context()
+    try:
+        M.ms_set_config(ctx.handle, dict(probe_variant=variant, map_cols=4, map_band_rows=64))
+        for k, (name, squares) in enumerate(_deep_rows_cases(TR, KC)):
+            announce("deep rows", variant, name)
+            rng = np.random.default_rng([variant, k])
+            m, n = 3 * TR + 7, 2100
+            a = (rng.random((m, n)) < 0.5).astype(np.uint8)
+            ta = TR  # tile row 1; tile column 1 owns columns 960..1919
+            for q, (off, side) in enumerate(squares):
+                r1 = ta + off
+                c1 = 1100 + q * 400  # the square's right column
+                a[r1 - side + 1:r1 + 1, c1 - side + 1:c1 + 1] = 1
+            assert_same(a, dev, ctx=ctx)
+    finally:
+        ctx.close()
+
+
 def test_resolve_falls_back_to_serial(dev):
     """A square so wide that the column-height window exceeds one word per lane: the serial
     pass finishes the matrix."""
