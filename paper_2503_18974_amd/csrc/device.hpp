@@ -806,8 +806,29 @@ __device__ __forceinline__ uint64_t row_from_left(uint64_t v, int32_t t, int lan
     return r ? ((a << r) | (b >> (64 - r))) : a;
 }
 
-// Bit j set iff bits j - k + 1 .. j of v's row are all set (log-doubling shift-AND).
+// Bit j set iff bits j - k + 1 .. j of v's row are all set.
+//  * k <= 64: log-doubling shift-AND; every shift is below 128 columns, so through DPP.
+//  * k > 64: a run of ones that long ending at bit j of a word covers all of the word's bits up
+//    to j (a run inside one word is at most 64 long), so only bits below the word's first zero
+//    qualify, each with the run j + 1 + e, e being the run entering the word from the left.
+//    e comes from the nearest lane to the left whose word has a zero: the ones at its top plus
+//    64 per full word between.  One ballot and one lane read instead of about log2(k) shifts,
+//    most of them lane permutes.
 __device__ __forceinline__ uint64_t row_erode(uint64_t v, int32_t k, int lane) {
+    if (k > 64) {
+        const bool full = v == ~0ull;
+        const uint64_t nonfull = __ballot(!full);
+        const int32_t top = full ? 64 : (int32_t)__clzll(~v);  // ones at the word's top
+        const uint64_t left = lane ? nonfull & (~0ull >> (64 - lane)) : 0ull;
+        const int p = left ? 63 - (int)__clzll(left) : -1;      // nearest such lane to the left
+        const int32_t top_p = __shfl(top, p < 0 ? 0 : p);
+        const int32_t enter = p < 0 ? 64 * lane : top_p + 64 * (lane - 1 - p);
+        const int32_t t = full ? 64 : __ffsll((long long)~v) - 1;  // ones at the word's bottom
+        const int32_t lo = k - 1 - enter;  // the first bit whose run reaches k
+        if (lo >= t) return 0ull;
+        const uint64_t below_t = t == 64 ? ~0ull : ((1ull << t) - 1);
+        return lo <= 0 ? below_t : below_t & ~((1ull << lo) - 1);
+    }
     int32_t a = 1;
     while (2 * a <= k) {
         v &= row_from_left(v, a, lane);
