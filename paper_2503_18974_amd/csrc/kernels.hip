@@ -750,25 +750,40 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->error, 2u);
         return;
     }
+    // each wave takes a contiguous run of items and walks it matrix by matrix: one lookup per
+    // matrix rather than per tile, and a matrix's tiles in row-major order, each seeing the best
+    // side its predecessors pushed
     const uint64_t wave = (uint64_t)wave_index();
     const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
+    const uint64_t per = (total + nwave - 1) / nwave;
+    uint64_t item = wave * per;
+    const uint64_t end = item + per < total ? item + per : total;
     SatBatch sb{sat};
-    sb.stride = (int64_t)nwave;
-    for (uint64_t item = wave; item < total; item += nwave) {
+    sb.stride = 1;
+    while (item < end) {
         const int64_t mi = ix.find(item);
         const ms_matrix d = mats[mi];
         const int64_t nwords = (d.n + 63) >> 6;
-        const int64_t t = (int64_t)(item - ix.start(mi));
-        if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n))) {
-            const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
-            const int64_t ty = t / ntx, tx = t - ty * ntx;
-            sb.add((int64_t)item, tile_search<TSN, false>(d.bits, d.m, d.n, d.ld_words, ty, tx,
-                                                          TileSink{keys + mi}));
-        } else {
-            const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
-            const int64_t ty = t / ntx, tx = t - ty * ntx;
-            sb.add((int64_t)item, tile_search<TS, false>(d.bits, d.m, d.n, d.ld_words, ty, tx,
-                                                         TileSink{keys + mi}));
+        const uint64_t st = ix.start(mi);
+        const bool narrow = uniform((int32_t)narrow_tiles<TS>(d.m, d.n)) != 0;
+        const int64_t ntx = narrow ? (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS
+                                   : (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
+        const uint64_t mend = st + (uint64_t)(narrow ? tile_count<TSN>(d.m, d.n)
+                                                     : tile_count<TS>(d.m, d.n));
+        const uint64_t stop = mend < end ? mend : end;  // > item: item is one of mi's tiles
+        const int64_t t = (int64_t)(item - st);
+        int64_t ty = t / ntx, tx = t - ty * ntx;
+        for (; item < stop; ++item) {
+            const int32_t r =
+                narrow ? tile_search<TSN, false>(d.bits, d.m, d.n, d.ld_words, ty, tx,
+                                                 TileSink{keys + mi})
+                       : tile_search<TS, false>(d.bits, d.m, d.n, d.ld_words, ty, tx,
+                                                TileSink{keys + mi});
+            sb.add((int64_t)item, r);
+            if (++tx == ntx) {
+                tx = 0;
+                ++ty;
+            }
         }
     }
     sb.flush();
