@@ -157,12 +157,15 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
 /*
  * Many matrices in one go.  h_mats is a host copy of the `count` descriptors whose device
  * copy is d_mats; results go to d_out[0 .. count-1] in the same order.  The tiles of all
- * matrices are spread over one grid-stride launch.  The tile total and a fingerprint of every
+ * matrices are spread over one probe launch.  The tile total and a fingerprint of every
  * descriptor's (index, m, n, ld_words) are computed on the host from h_mats and checked on the
  * device against d_mats; when the two copies disagree, every result is side -1 instead of a
- * search (the Python binding raises).  With the environment variable MAXSQ_GRAPH=1
- * the launch sequence is captured once per (descriptors, shapes, output, workspace) into a HIP
- * graph and replayed on later calls.
+ * search (the Python binding raises).
+ * Submission: the first call with a given (d_mats, count, d_out, d_workspace, shapes, probe
+ * variant) enqueues its launches one by one; a repeat of it is captured once into a HIP graph
+ * (at most 8 kept per context) and replayed from then on, one submission per call.  A stream
+ * under capture by the caller always gets the launches themselves.  See ms_set_batched_graphs
+ * (and the MAXSQ_GRAPH environment variable) to turn the graphs off or capture at once.
  * The caller provides the workspace (size from ms_batched_workspace_size with the same
  * descriptors; that size fits every probe variant); the library keeps no pointer to it after
  * the work completes.
@@ -256,6 +259,15 @@ ms_status ms_autotune_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_mat
                               size_t workspace_bytes, void *stream);
 ms_status ms_autotune_save(ms_ctx *ctx, const char *path);
 ms_status ms_autotune_load(ms_ctx *ctx, const char *path);
+
+/* How ms_max_square_batched submits its launches on this context: MS_GRAPHS_ON_REPEAT (the
+ * default: a repeated batch is captured once into a HIP graph and replayed), MS_GRAPHS_OFF
+ * (launches enqueued one by one: a serving loop whose batches rarely repeat, where a capture
+ * or a graph eviction would land in a request's latency) or MS_GRAPHS_ALWAYS (captured on the
+ * first call).  The environment variable MAXSQ_GRAPH, when set to 0 or 1, overrides it.
+ * Invalid: a mode outside these three. */
+enum { MS_GRAPHS_OFF = 0, MS_GRAPHS_ON_REPEAT = 1, MS_GRAPHS_ALWAYS = 2 };
+ms_status ms_set_batched_graphs(ms_ctx *ctx, int mode);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ __all__ = [
     "MaxsqError", "Square", "lib", "library_path", "ms_create", "ms_destroy", "ms_pack_u8",
     "ms_max_square", "ms_max_square_noalloc", "ms_square_map", "ms_square_map_from_max", "ms_batched_workspace_size", "ms_max_square_batched",
     "ms_set_config", "ms_get_config", "ms_candidate", "ms_num_candidates", "ms_autotune",
-    "ms_autotune_save", "ms_autotune_load", "Context", "pack_u8", "max_square", "square_map",
+    "ms_autotune_save", "ms_autotune_load", "ms_set_batched_graphs", "GRAPHS_OFF",
+    "GRAPHS_ON_REPEAT", "GRAPHS_ALWAYS", "Context", "pack_u8", "max_square", "square_map",
     "max_square_batched", "square_map_from_max", "area", "words_per_row",
     "Rect", "ms_max_rectangle", "max_rectangle", "Cube", "ms_max_cube",
     "ms_max_cube_workspace_size", "max_cube",
@@ -128,6 +129,7 @@ def lib():
             "ms_max_cube": [_P, _P, _I64, _I64, _I64, _I64, _P, _P, ctypes.c_size_t, _P],
             "ms_autotune_save": [_P, ctypes.c_char_p],
             "ms_autotune_load": [_P, ctypes.c_char_p],
+            "ms_set_batched_graphs": [_P, ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -198,6 +200,14 @@ def ms_candidate(i: int) -> dict:
     _check(lib().ms_candidate(i, ctypes.byref(c)), "ms_candidate")
     return {"probe_variant": c.probe_variant, "map_cols": c.map_cols,
             "map_band_rows": c.map_band_rows}
+
+
+GRAPHS_OFF, GRAPHS_ON_REPEAT, GRAPHS_ALWAYS = 0, 1, 2
+
+
+def ms_set_batched_graphs(ctx, mode: int) -> None:
+    """How batched calls on ctx submit their launches (see include/maxsq.h)."""
+    _check(lib().ms_set_batched_graphs(ctx, int(mode)), "ms_set_batched_graphs")
 
 
 def ms_set_config(ctx, cfg: dict | None) -> None:

@@ -40,24 +40,26 @@ struct GraphEntry {
     const void *out;
     const void *ws;
     int variant;
+    int narrow;  // tile-width weight
     uint64_t shape_hash;
     hipGraphExec_t exec;
 };
 
+// Identity of a batch's shapes for the graph cache: four independent multiply-xor lanes over
+// (m, n, ld_words) words (a byte-wise hash costs a dependent multiply per byte, about 0.3 ms per
+// 10000 descriptors, as long as the device needs for the whole search).
 uint64_t shape_hash(const ms_matrix *h_mats, int64_t count) {
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over the shape words
-    auto mix = [&h](uint64_t v) {
-        for (int b = 0; b < 8; ++b) {
-            h ^= (v >> (8 * b)) & 0xff;
-            h *= 1099511628211ull;
-        }
-    };
+    uint64_t h[4] = {0x9E3779B97F4A7C15ull, 0xC2B2AE3D27D4EB4Full, 0x165667B19E3779F9ull,
+                     0xD6E8FEB86659FD93ull};
     for (int64_t i = 0; i < count; ++i) {
-        mix((uint64_t)h_mats[i].m);
-        mix((uint64_t)h_mats[i].n);
-        mix((uint64_t)h_mats[i].ld_words);
+        uint64_t &a = h[i & 3];
+        a = (a ^ (uint64_t)h_mats[i].m) * 0xBF58476D1CE4E5B9ull;
+        a = (a ^ (uint64_t)h_mats[i].n) * 0x94D049BB133111EBull;
+        a = (a ^ (uint64_t)h_mats[i].ld_words) * 0xBF58476D1CE4E5B9ull;
     }
-    return h;
+    uint64_t r = (uint64_t)count;
+    for (int k = 0; k < 4; ++k) r = (r ^ h[k] ^ (h[k] >> 29)) * 0x94D049BB133111EBull;
+    return r ^ (r >> 32);
 }
 
 }  // namespace
@@ -73,8 +75,11 @@ struct ms_ctx {
     bool has_forced = false;
     ms_config forced{};
     int batched_variant = -1;  // from ms_autotune_batched (or a loaded table); -1: default
+    int batched_narrow = -1;   // its tile-width weight; -1: the default weight
+    int graph_mode = MS_GRAPHS_ON_REPEAT;  // ms_set_batched_graphs
     std::map<int, ms_config> tuned;
     std::vector<GraphEntry> graphs;
+    std::vector<GraphEntry> seen;  // batches run once eagerly (exec unused): a repeat is captured
     hipStream_t capture_stream = nullptr;
     // largest-rectangle scratch: header | one record per block of the launch
     void *rect_scratch = nullptr;
@@ -468,10 +473,8 @@ ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_
     }
     if (count >= (int64_t(1) << 24)) return MS_ERR_INVALID_ARGUMENT;
     (void)ctx;
-    size_t need = 0;  // enough for every variant, so a tuned choice always fits
-    for (int v = 0; v < mshost::NUM_PROBE_VARIANTS; ++v)
-        need = std::max(need, mshost::batch_layout(v, h_mats, count).total);
-    *bytes = need;
+    // a bound for every probe variant and tile width, so a tuned choice always fits
+    *bytes = mshost::batch_layout(0, -1, h_mats, count).total;
     return MS_OK;
 }
 
@@ -493,20 +496,43 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
     const int variant = c->has_forced ? c->forced.probe_variant
                         : c->batched_variant >= 0 ? c->batched_variant
                                                   : DEFAULT_CONFIG.probe_variant;
-    const mshost::BatchLayout L = mshost::batch_layout(variant, h_mats, count);
+    const int narrow = !c->has_forced && c->batched_narrow >= 0 ? c->batched_narrow
+                                                                : mshost::NARROW_WEIGHTS[0];
+    const mshost::BatchLayout L = mshost::batch_layout(variant, narrow, h_mats, count);
     if (workspace_bytes < L.total) return MS_ERR_WORKSPACE_TOO_SMALL;
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
     hipStream_t st = (hipStream_t)stream;
+    // a batch met for the first time runs its launches eagerly and is remembered; a repeat of
+    // it (same descriptor, output and workspace buffers, count, variant and shapes) is captured
+    // once into a graph and replayed from then on: one submission per call (the context's
+    // graph mode, or MAXSQ_GRAPH=0 / 1, turns this off or captures on the first call).
+    // A stream the caller is capturing records the eager launches into the caller's graph.
     const char *gv = std::getenv("MAXSQ_GRAPH");
-    if (!(gv && gv[0] == '1')) {
-        mshost::LaunchEnv env{c->num_cus, st};
-        return hip_status(mshost::launch_batched(env, variant, d_mats, count, d_out, d_workspace, L));
-    }
+    const int mode = gv && gv[0] == '0'   ? MS_GRAPHS_OFF
+                     : gv && gv[0] == '1' ? MS_GRAPHS_ALWAYS
+                                          : c->graph_mode;
+    mshost::LaunchEnv eager{c->num_cus, st};
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) return MS_ERR_HIP;
+    if (mode == MS_GRAPHS_OFF || cap != hipStreamCaptureStatusNone)
+        return hip_status(mshost::launch_batched(eager, variant, d_mats, count, d_out, d_workspace, L));
     const uint64_t sh = shape_hash(h_mats, count);
-    for (auto &g : c->graphs) {
-        if (g.mats == d_mats && g.count == count && g.out == d_out && g.ws == d_workspace &&
-            g.variant == variant && g.shape_hash == sh)
-            return hip_status(hipGraphLaunch(g.exec, st));
+    const auto same = [&](const GraphEntry &g) {
+        return g.mats == d_mats && g.count == count && g.out == d_out && g.ws == d_workspace &&
+               g.variant == variant && g.narrow == narrow && g.shape_hash == sh;
+    };
+    for (auto &g : c->graphs)
+        if (same(g)) return hip_status(hipGraphLaunch(g.exec, st));
+    if (mode == MS_GRAPHS_ON_REPEAT) {
+        bool repeat = false;
+        for (size_t k = 0; k < c->seen.size() && !repeat; ++k) repeat = same(c->seen[k]);
+        if (!repeat) {
+            if (c->seen.size() >= 16) c->seen.erase(c->seen.begin());
+            c->seen.push_back(
+                GraphEntry{d_mats, count, d_out, d_workspace, variant, narrow, sh, nullptr});
+            return hip_status(
+                mshost::launch_batched(eager, variant, d_mats, count, d_out, d_workspace, L));
+        }
     }
     if (!c->capture_stream) {
         if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
@@ -531,7 +557,7 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
         (void)hipGraphExecDestroy(c->graphs.front().exec);
         c->graphs.erase(c->graphs.begin());
     }
-    c->graphs.push_back(GraphEntry{d_mats, count, d_out, d_workspace, variant, sh, exec});
+    c->graphs.push_back(GraphEntry{d_mats, count, d_out, d_workspace, variant, narrow, sh, exec});
     return hip_status(hipGraphLaunch(exec, st));
 }
 
@@ -754,6 +780,17 @@ ms_status ms_set_config(ms_ctx *ctx, const ms_config *cfg) {
     return MS_OK;
 }
 
+ms_status ms_set_batched_graphs(ms_ctx *ctx, int mode) {
+    if (mode != MS_GRAPHS_OFF && mode != MS_GRAPHS_ON_REPEAT && mode != MS_GRAPHS_ALWAYS)
+        return MS_ERR_INVALID_ARGUMENT;
+    ms_ctx *c = nullptr;
+    ms_status s = resolve(ctx, &c);
+    if (s != MS_OK) return s;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->graph_mode = mode;
+    return MS_OK;
+}
+
 ms_status ms_get_config(ms_ctx *ctx, int64_t m, int64_t n, ms_config *cfg) {
     if (!cfg || m < 0 || n < 0) return MS_ERR_INVALID_ARGUMENT;
     if (!ctx) {
@@ -864,40 +901,48 @@ ms_status ms_autotune_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_mat
         return MS_ERR_HIP;
     }
     mshost::LaunchEnv env{c->num_cus, st};
-    int best_v = DEFAULT_CONFIG.probe_variant;
+    int best_v = DEFAULT_CONFIG.probe_variant, best_q = mshost::NARROW_WEIGHTS[0];
     float best_t = 1e30f;
+    // every probe variant with every tile-width weight
     for (int v = 0; v < mshost::NUM_PROBE_VARIANTS && s == MS_OK; ++v) {
-        const mshost::BatchLayout L = mshost::batch_layout(v, h_mats, count);
-        if (workspace_bytes < L.total) {
-            s = MS_ERR_WORKSPACE_TOO_SMALL;
-            break;
-        }
-        const int reps = 3;
-        hipError_t e = mshost::launch_batched(env, v, d_mats, count, d_out, d_workspace, L);
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = mshost::launch_batched(env, v, d_mats, count, d_out, d_workspace, L);
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            s = hip_status(e);
-            break;
-        }
-        if (ms < best_t) {
-            best_t = ms;
-            best_v = v;
+        for (int k = 0; k < mshost::NUM_NARROW_WEIGHTS && s == MS_OK; ++k) {
+            const int q = mshost::NARROW_WEIGHTS[k];
+            const mshost::BatchLayout L = mshost::batch_layout(v, q, h_mats, count);
+            if (workspace_bytes < L.total) {
+                s = MS_ERR_WORKSPACE_TOO_SMALL;
+                break;
+            }
+            const int reps = 3;
+            hipError_t e = mshost::launch_batched(env, v, d_mats, count, d_out, d_workspace, L);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = mshost::launch_batched(env, v, d_mats, count, d_out, d_workspace, L);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                s = hip_status(e);
+                break;
+            }
+            if (ms < best_t) {
+                best_t = ms;
+                best_v = v;
+                best_q = q;
+            }
         }
     }
-    // leave the results of the chosen variant in d_out
+    // leave the results of the chosen launch shape in d_out
     if (s == MS_OK) {
-        const mshost::BatchLayout L = mshost::batch_layout(best_v, h_mats, count);
+        const mshost::BatchLayout L = mshost::batch_layout(best_v, best_q, h_mats, count);
         s = hip_status(mshost::launch_batched(env, best_v, d_mats, count, d_out, d_workspace, L));
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (s == MS_OK) c->batched_variant = best_v;
+    if (s == MS_OK) {
+        c->batched_variant = best_v;
+        c->batched_narrow = best_q;
+    }
     return s;
 }
 
@@ -906,8 +951,11 @@ ms_status ms_autotune_save(ms_ctx *ctx, const char *path) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     FILE *f = std::fopen(path, "w");
     if (!f) return MS_ERR_INVALID_ARGUMENT;
-    std::fprintf(f, "# maxsq autotune table: bucket probe_variant map_cols map_band_rows\n");
-    if (ctx->batched_variant >= 0) std::fprintf(f, "batched %d\n", ctx->batched_variant);
+    std::fprintf(f, "# maxsq autotune table: bucket probe_variant map_cols map_band_rows; "
+                    "batched probe_variant tile_width_weight\n");
+    if (ctx->batched_variant >= 0)
+        std::fprintf(f, "batched %d %d\n", ctx->batched_variant,
+                     ctx->batched_narrow >= 0 ? ctx->batched_narrow : mshost::NARROW_WEIGHTS[0]);
     for (auto &kv : ctx->tuned)
         std::fprintf(f, "%d %d %d %d\n", kv.first, kv.second.probe_variant, kv.second.map_cols,
                      kv.second.map_band_rows);
@@ -920,18 +968,20 @@ ms_status ms_autotune_load(ms_ctx *ctx, const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return MS_ERR_INVALID_ARGUMENT;
     std::map<int, ms_config> table;
-    int batched = -1;
+    int batched = -1, batched_q = -1;
     char line[256];
     ms_status s = MS_OK;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
-        int bv = -1;
-        if (std::sscanf(line, "batched %d", &bv) == 1) {
-            if (bv < 0 || bv >= mshost::NUM_PROBE_VARIANTS) {
+        int bv = -1, bq = mshost::NARROW_WEIGHTS[0];
+        const int nb = std::sscanf(line, "batched %d %d", &bv, &bq);
+        if (nb >= 1) {  // "batched <variant> [<tile-width weight>]"
+            if (bv < 0 || bv >= mshost::NUM_PROBE_VARIANTS || !mshost::narrow_weight_valid(bq)) {
                 s = MS_ERR_INVALID_ARGUMENT;
                 break;
             }
             batched = bv;
+            batched_q = bq;
             continue;
         }
         int b = 0;
@@ -947,7 +997,10 @@ ms_status ms_autotune_load(ms_ctx *ctx, const char *path) {
     if (s != MS_OK) return s;
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &kv : table) ctx->tuned[kv.first] = kv.second;
-    if (batched >= 0) ctx->batched_variant = batched;
+    if (batched >= 0) {
+        ctx->batched_variant = batched;
+        ctx->batched_narrow = batched_q;
+    }
     return MS_OK;
 }
 

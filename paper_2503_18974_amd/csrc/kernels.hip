@@ -582,16 +582,20 @@ __host__ __device__ __forceinline__ int64_t tile_count(int64_t m, int64_t n) {
     return ((m + TS::TR - 1) / TS::TR) * ((nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS);
 }
 
+// The tile width of one matrix: narrow when 4 x its narrow-tile work is below q x its wide-tile
+// work.  q = NARROW_DEFAULT compares the two works as they are; the batched autotuner also tries
+// 0 (never narrow), 2 and 8 (narrow when its work is below half, or twice, the wide tile's).
+constexpr int NARROW_DEFAULT = 4;
 template <class TS>
-__host__ __device__ __forceinline__ bool narrow_tiles(int64_t m, int64_t n) {
-    return tile_count<TSN>(m, n) * TSN::RPL < tile_count<TS>(m, n) * TS::RPL;
+__host__ __device__ __forceinline__ bool narrow_tiles(int64_t m, int64_t n, int q) {
+    return tile_count<TSN>(m, n) * TSN::RPL * 4 < tile_count<TS>(m, n) * TS::RPL * q;
 }
 
 // Tiles of one matrix of a batch whose wide tile is TS.
 template <class TS>
-__device__ __forceinline__ uint64_t tiles_in(const ms_matrix &d) {
-    return (uint64_t)(narrow_tiles<TS>(d.m, d.n) ? tile_count<TSN>(d.m, d.n)
-                                                  : tile_count<TS>(d.m, d.n));
+__device__ __forceinline__ uint64_t tiles_in(const ms_matrix &d, int q) {
+    return (uint64_t)(narrow_tiles<TS>(d.m, d.n, q) ? tile_count<TSN>(d.m, d.n)
+                                                     : tile_count<TS>(d.m, d.n));
 }
 
 // Fingerprint of a batch's shapes: the wrapping sum over i of a mix of (i, m, n, ld_words),
@@ -653,7 +657,7 @@ __global__ __launch_bounds__(INIT_BLOCK) void k_batch_count(const ms_matrix *__r
                                                             uint64_t *__restrict__ local,
                                                             uint32_t *__restrict__ flags,
                                                             InitPart *__restrict__ parts,
-                                                            BatchCounters *ctr) {
+                                                            BatchCounters *ctr, int q) {
     constexpr int NW = INIT_BLOCK / WAVE;
     __shared__ uint64_t wt[NW], wm[NW];
     const int lane = __lane_id(), wv = threadIdx.x / WAVE;
@@ -663,7 +667,7 @@ __global__ __launch_bounds__(INIT_BLOCK) void k_batch_count(const ms_matrix *__r
         const ms_matrix d = mats[i];
         keys[i] = 0;
         flags[i] = 0;
-        t = tiles_in<TS>(d);
+        t = tiles_in<TS>(d, q);
         h = shape_mix((uint64_t)i, (uint64_t)d.m, (uint64_t)d.n, (uint64_t)d.ld_words);
     }
     uint64_t incl = t, hs = h;  // inclusive scan of t and sum of h over the wave
@@ -742,7 +746,8 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
                                                        const uint64_t *__restrict__ off,
                                                        int64_t count, int64_t nblk,
                                                        BatchCounters *ctr,
-                                                       uint8_t *__restrict__ sat, uint64_t total) {
+                                                       uint8_t *__restrict__ sat, uint64_t total,
+                                                       int q) {
     // the index arrays come in as restrict-qualified kernel arguments (nothing in the kernel
     // writes them), so their wave-uniform reads can go through the scalar cache
     const BatchIndex ix{local, off, count, nblk};
@@ -765,7 +770,7 @@ __global__ __launch_bounds__(256) void k_probe_batched(const ms_matrix *__restri
         const ms_matrix d = mats[mi];
         const int64_t nwords = (d.n + 63) >> 6;
         const uint64_t st = ix.start(mi);
-        const bool narrow = uniform((int32_t)narrow_tiles<TS>(d.m, d.n)) != 0;
+        const bool narrow = uniform((int32_t)narrow_tiles<TS>(d.m, d.n, q)) != 0;
         const int64_t ntx = narrow ? (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS
                                    : (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
         const uint64_t mend = st + (uint64_t)(narrow ? tile_count<TSN>(d.m, d.n)
@@ -829,7 +834,8 @@ __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restric
                                                       BatchCounters *ctr,
                                                       const uint8_t *__restrict__ sat,
                                                       uint64_t total, int32_t *serial_state,
-                                                      int64_t state_words, ms_square *out) {
+                                                      int64_t state_words, ms_square *out,
+                                                      int q) {
     const int lane = __lane_id();
     const BatchIndex ix{local, off, count, nblk};
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -859,7 +865,7 @@ __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restric
             const int64_t nwords = (d.n + 63) >> 6;
             const uint64_t st = ix.start(mi);
             const int64_t t = (int64_t)(item - st);
-            if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n))) {
+            if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n, q))) {
                 const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
                 const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
                 resolve_tile<TSN>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx, sat + st,
@@ -1244,29 +1250,44 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Tiles of one matrix of a batch whose wide tile is TS (the device's rule, msk::tiles_in).
 template <class TS>
-static uint64_t tiles_of(const ms_matrix &d) {
-    return (uint64_t)(msk::narrow_tiles<TS>(d.m, d.n) ? msk::tile_count<msk::TSN>(d.m, d.n)
-                                                       : msk::tile_count<TS>(d.m, d.n));
+static uint64_t tiles_of(const ms_matrix &d, int q) {
+    return (uint64_t)(msk::narrow_tiles<TS>(d.m, d.n, q) ? msk::tile_count<msk::TSN>(d.m, d.n)
+                                                          : msk::tile_count<TS>(d.m, d.n));
 }
 
-BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
+bool narrow_weight_valid(int q) {
+    for (int k = 0; k < NUM_NARROW_WEIGHTS; ++k)
+        if (NARROW_WEIGHTS[k] == q) return true;
+    return false;
+}
+const int NARROW_WEIGHTS[NUM_NARROW_WEIGHTS] = {msk::NARROW_DEFAULT, 0, 2, 8};
+
+BatchLayout batch_layout(int variant, int q, const ms_matrix *h_mats, int64_t count) {
     BatchLayout L{};
-    uint64_t tiles = 0;
-    int64_t maxw = 1;
-    for (int64_t i = 0; i < count; ++i) {
-        switch (variant) {
-        case 0: tiles += tiles_of<TS0>(h_mats[i]); break;
-        case 1: tiles += tiles_of<TS1>(h_mats[i]); break;
-        default: tiles += tiles_of<TS2>(h_mats[i]); break;
+    L.narrow_q = q;
+    uint64_t tiles = 0, mix = 0;
+    int64_t maxn = 1;
+    const auto pass = [&](auto ts) {  // one pass: tiles, widest row, fingerprint
+        using TS = decltype(ts);
+        for (int64_t i = 0; i < count; ++i) {
+            const ms_matrix &d = h_mats[i];
+            tiles += q >= 0 ? tiles_of<TS>(d, q)  // q < 0: a bound for every tile choice
+                            : std::max<uint64_t>({(uint64_t)msk::tile_count<TS0>(d.m, d.n),
+                                                  (uint64_t)msk::tile_count<TS1>(d.m, d.n),
+                                                  (uint64_t)msk::tile_count<TS2>(d.m, d.n),
+                                                  (uint64_t)msk::tile_count<msk::TSN>(d.m, d.n)});
+            maxn = std::max<int64_t>(maxn, d.n);
+            mix += msk::shape_mix((uint64_t)i, (uint64_t)d.m, (uint64_t)d.n,
+                                  (uint64_t)d.ld_words);
         }
-        maxw = std::max<int64_t>(maxw, cdiv(std::max<int64_t>(h_mats[i].n, 1), 64));
+    };
+    switch (variant) {
+    case 0: pass(TS0{}); break;
+    case 1: pass(TS1{}); break;
+    default: pass(TS2{}); break;
     }
     L.total_tiles = tiles;
-    L.max_nwords = maxw;
-    uint64_t mix = 0;
-    for (int64_t i = 0; i < count; ++i)
-        mix += msk::shape_mix((uint64_t)i, (uint64_t)h_mats[i].m, (uint64_t)h_mats[i].n,
-                              (uint64_t)h_mats[i].ld_words);
+    L.max_nwords = cdiv(maxn, 64);
     L.shape_mix = mix;
     size_t off = 0;
     L.counters = off; off = align256(off + sizeof(msk::BatchCounters));
@@ -1276,7 +1297,7 @@ BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count) {
     L.parts = off; off = align256(off + sizeof(msk::InitPart) * (size_t)L.nblk);
     L.offsets = off; off = align256(off + sizeof(uint64_t) * (size_t)(L.nblk + 1));
     L.flags = off; off = align256(off + sizeof(uint32_t) * (size_t)count);
-    L.serial_state = off; off = align256(off + sizeof(int32_t) * 2 * 64 * (size_t)maxw);
+    L.serial_state = off; off = align256(off + sizeof(int32_t) * 2 * 64 * (size_t)L.max_nwords);
     L.sat = off; off = align256(off + (size_t)tiles);
     L.total = off;
     return L;
@@ -1296,7 +1317,7 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
     // setup: per-matrix tile starts within init blocks and the blocks' totals, then the blocks'
     // starts and the fingerprint check
     hipLaunchKernelGGL(msk::k_batch_count<TS>, dim3((unsigned)L.nblk), dim3(msk::INIT_BLOCK), 0,
-                       env.stream, mats, count, keys, local, flags, parts, ctr);
+                       env.stream, mats, count, keys, local, flags, parts, ctr, L.narrow_q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(msk::k_batch_offsets, dim3(1), dim3(1024), 0, env.stream, parts, L.nblk,
@@ -1306,7 +1327,7 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
         1, std::min<int64_t>(cdiv((int64_t)L.total_tiles, 4), (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_probe_batched<TS>, dim3((unsigned)pblocks), dim3(256), 0,
                        env.stream, mats, keys, local, offs, count, L.nblk, ctr, sat,
-                       (uint64_t)L.total_tiles);
+                       (uint64_t)L.total_tiles, L.narrow_q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // results, and the saturated tiles first if any (one launch)
     const int64_t fblocks = std::max<int64_t>(
@@ -1314,7 +1335,7 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
                              (int64_t)env.num_cus * 2));
     hipLaunchKernelGGL(msk::k_batch_finish<TS>, dim3((unsigned)fblocks), dim3(256), 0,
                        env.stream, mats, keys, local, offs, count, L.nblk, flags, ctr, sat,
-                       (uint64_t)L.total_tiles, state, L.max_nwords, out);
+                       (uint64_t)L.total_tiles, state, L.max_nwords, out, L.narrow_q);
     return hipGetLastError();
 }
 

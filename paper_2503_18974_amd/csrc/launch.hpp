@@ -108,8 +108,15 @@ struct BatchLayout {
     uint64_t total_tiles;
     int64_t max_nwords;
     uint64_t shape_mix;  // fingerprint of every (i, m, n, ld_words), checked on the device
+    int narrow_q;        // tile-width weight (see msk::narrow_tiles); -1 for a size bound
 };
-BatchLayout batch_layout(int variant, const ms_matrix *h_mats, int64_t count);
+// Tile-width weights the batched autotuner tries (the first is the default).
+constexpr int NUM_NARROW_WEIGHTS = 4;
+extern const int NARROW_WEIGHTS[NUM_NARROW_WEIGHTS];
+bool narrow_weight_valid(int q);
+// Layout for probe variant `variant` and tile-width weight q; with q = -1 the sizes bound every
+// variant and weight (the workspace size of the batched entry point).
+BatchLayout batch_layout(int variant, int q, const ms_matrix *h_mats, int64_t count);
 hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_mats,
                           int64_t count, ms_square *out, void *ws, const BatchLayout &L);
 

@@ -401,9 +401,14 @@ class GpuExecutor:
         for i in range(self.max_batch):
             probe[i] = _Matrix(1, max_n, max_n, (max_n + 63) // 64)
         ws_bytes = ms_batched_workspace_size(None, probe, self.max_batch)
+        from . import ms_set_batched_graphs, GRAPHS_OFF
         for _ in range(int(slots)):
+            ctx = Context(device)
+            # a slot's buffers are reused by batches of the same shapes now and then: no graph
+            # capture (or eviction, which waits for the device) inside a request's latency
+            ms_set_batched_graphs(ctx.handle, GRAPHS_OFF)
             self.slots.append({
-                "ctx": Context(device),
+                "ctx": ctx,
                 "stream": torch.cuda.Stream(device=self.dev),
                 "d_mats": torch.empty(self.max_batch * msz, dtype=torch.uint8, device=self.dev),
                 "h_mats": (_Matrix * self.max_batch)(),

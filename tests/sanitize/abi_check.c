@@ -122,6 +122,8 @@ int main(void) {
     ms_config c;
     expect("candidate past end", ms_candidate(nc, &c), MS_ERR_INVALID_ARGUMENT);
     expect("candidate null", ms_candidate(0, NULL), MS_ERR_INVALID_ARGUMENT);
+    expect("graph mode -1", ms_set_batched_graphs(NULL, -1), MS_ERR_INVALID_ARGUMENT);
+    expect("graph mode 3", ms_set_batched_graphs(NULL, 3), MS_ERR_INVALID_ARGUMENT);
     expect("autotune save null", ms_autotune_save(NULL, "x"), MS_ERR_INVALID_ARGUMENT);
     expect("destroy null", ms_destroy(NULL), MS_ERR_INVALID_ARGUMENT);
 

@@ -112,6 +112,9 @@ def test_candidates_and_config_validation():
     bad = M._Config(0, 5, 64)
     assert L.ms_set_config(None, ctypes.byref(bad)) == INVALID
     assert L.ms_candidate(n, ctypes.byref(M._Config())) == INVALID
+    # batched submission modes: only the three declared ones (checked before any context)
+    for mode in (-1, 3, 99):
+        assert L.ms_set_batched_graphs(None, mode) == INVALID
 
 
 def test_default_config_by_size():

@@ -34,9 +34,12 @@ def test_autotune_single_matrix_and_table(dev, tmp_path):
     M.ms_autotune_load(ctx2.handle, path)
     assert M.ms_get_config(ctx2.handle, m, n) == cfg
     bad = tmp_path / "bad.txt"
-    bad.write_text("1 9 4 64\n")                       # probe variant out of range
-    with pytest.raises(M.MaxsqError):
-        M.ms_autotune_load(ctx2.handle, str(bad))
+    for text in ("1 9 4 64\n",        # probe variant out of range
+                 "batched 1 3\n",     # tile-width weight not among the tuned ones
+                 "batched 5 4\n"):    # batched probe variant out of range
+        bad.write_text(text)
+        with pytest.raises(M.MaxsqError):
+            M.ms_autotune_load(ctx2.handle, str(bad))
     assert M.ms_get_config(ctx2.handle, m, n) == cfg   # a rejected table changes nothing
     ctx.close()
     ctx2.close()
@@ -64,7 +67,9 @@ def test_autotune_batched(dev, tmp_path):
     assert [(s.side, s.row, s.col) for s in b.results()] == refs
     path = str(tmp_path / "table.txt")
     M.ms_autotune_save(ctx.handle, path)
-    assert any(line.startswith("batched ") for line in open(path))
+    batched = [line.split() for line in open(path) if line.startswith("batched ")]
+    assert len(batched) == 1 and len(batched[0]) == 3          # variant and tile-width weight
+    assert int(batched[0][1]) in (0, 1, 2) and int(batched[0][2]) in (4, 0, 2, 8)
     ctx2 = M.Context()
     M.ms_autotune_load(ctx2.handle, path)
     b2 = M.Batch(items, ctx=ctx2)

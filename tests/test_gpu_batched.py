@@ -121,12 +121,25 @@ def test_batched_repeat_reuses_workspace(dev):
         assert [(g.side, g.row, g.col) for g in got] == refs
 
 
-def test_batched_graph_replays(dev, monkeypatch):
+# MAXSQ_GRAPH unset: the library's default (a repeated batch is captured on its second call
+# and replayed after); "1": captured on the first call; "0": eager launches only.
+GRAPH_MODES = [None, "1", "0"]
+
+
+def _graph_mode(monkeypatch, mode):
+    if mode is None:
+        monkeypatch.delenv("MAXSQ_GRAPH", raising=False)
+    else:
+        monkeypatch.setenv("MAXSQ_GRAPH", mode)
+
+
+@pytest.mark.parametrize("mode", GRAPH_MODES)
+def test_batched_graph_replays(dev, monkeypatch, mode):
     """The launch sequence recorded once into a HIP graph: every replay (with eager work and
     synchronisation between replays) gives the oracle's results."""
     import torch
-    announce("batched graph")
-    monkeypatch.setenv("MAXSQ_GRAPH", "1")
+    announce("batched graph", mode)
+    _graph_mode(monkeypatch, mode)
     mats = make_mix(5, 16)
     items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
     b = M.Batch(items)
@@ -142,13 +155,38 @@ def test_batched_graph_replays(dev, monkeypatch):
         assert (single.side, single.row, single.col) == refs[k]
 
 
-def test_batched_graph_same_buffers_new_shapes(dev, monkeypatch):
+@pytest.mark.parametrize("mode", [M.GRAPHS_OFF, M.GRAPHS_ON_REPEAT, M.GRAPHS_ALWAYS])
+def test_batched_context_graph_modes(dev, monkeypatch, mode):
+    """The per-context submission mode (no MAXSQ_GRAPH override): four calls of one batch on
+    one context, each equal to the oracle."""
+    import torch
+    announce("batched context graph mode", mode)
+    monkeypatch.delenv("MAXSQ_GRAPH", raising=False)
+    mats = make_mix(9, 12)
+    items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in mats]
+    refs = [oracle.max_square(a) for a in mats]
+    ctx = M.Context()
+    try:
+        M.ms_set_batched_graphs(ctx.handle, mode)
+        b = M.Batch(items, ctx=ctx)
+        for k in range(4):
+            b.out.fill_(-6)
+            b.run()
+            torch.cuda.synchronize()
+            assert [(g.side, g.row, g.col) for g in b.results()] == refs, "call %d" % k
+        del b
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("mode", GRAPH_MODES)
+def test_batched_graph_same_buffers_new_shapes(dev, monkeypatch, mode):
     """Graph mode with the descriptor buffer, count, output and workspace reused for a batch
-    of different shapes: the second call must not replay the first call's launch sequence."""
+    of different shapes: no call may replay another shape set's launch sequence."""
     import ctypes
     import torch
-    announce("batched graph new shapes")
-    monkeypatch.setenv("MAXSQ_GRAPH", "1")
+    announce("batched graph new shapes", mode)
+    _graph_mode(monkeypatch, mode)
     sets = [make_mix(6, 10), make_mix(7, 10)]
     items = [[(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for a in s] for s in sets]
     count = 10
@@ -161,8 +199,8 @@ def test_batched_graph_same_buffers_new_shapes(dev, monkeypatch):
     d_mats = torch.empty(ctypes.sizeof(M._Matrix) * count, dtype=torch.uint8, device=dev)
     out = torch.empty((count, 3), dtype=torch.int64, device=dev)
     sp = torch.cuda.current_stream().cuda_stream
-    for rep in range(2):
-        for k in range(2):
+    for rep in range(3):
+        for k in (0, 0, 1) if rep < 2 else (1, 0):
             raw = bytes(h[k])
             d_mats.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
             out.fill_(-7)

@@ -70,9 +70,10 @@ def test_large_config(dev, name):
         assert [r.area, r.row, r.col, r.height, r.width] == g["rect"]
 
 
-def test_c4_batched_full(dev):
-    """All 10000 matrices of the batched workload in one batched call, and each through the
-    plain single-matrix call, against the oracle's stored results."""
+def test_c4_batched_full(dev, tmp_path):
+    """All 10000 matrices of the batched workload in one batched call (default launch shape,
+    then every shape the batched autotuner can choose), and each through the plain
+    single-matrix call, against the oracle's stored results."""
     import torch
     path = os.path.join(os.path.dirname(__file__), "golden", "c4_results.txt")
     lines = open(path).read().splitlines()
@@ -89,6 +90,29 @@ def test_c4_batched_full(dev):
     got = np.array([[s.side, s.row, s.col] for s in M.max_square_batched(items)])
     bad = np.flatnonzero(np.any(got != ref[:, 3:6], axis=1))
     assert bad.size == 0, "matrix %d: %s vs oracle %s" % (bad[0], got[bad[0]], ref[bad[0], 3:6])
+    # every launch shape the batched autotuner can choose (probe tile x tile-width weight),
+    # each forced through a loaded tuning table on a fresh context, run twice (the second
+    # call is replayed from a captured graph)
+    for v in range(3):
+        for q in (4, 0, 2, 8):
+            announce("large", "c4", "batched candidate", v, q)
+            table = os.path.join(tmp_path, "c4_%d_%d.txt" % (v, q))
+            with open(table, "w") as f:
+                f.write("batched %d %d\n" % (v, q))
+            ctx = M.Context()
+            try:
+                M.ms_autotune_load(ctx.handle, table)
+                b = M.Batch(items, ctx=ctx)
+                for _ in range(2):
+                    b.out.fill_(-4)
+                    b.run()
+                    got = np.array(b.out[:len(ref)].cpu().tolist())
+                    bad = np.flatnonzero(np.any(got != ref[:, 3:6], axis=1))
+                    assert bad.size == 0, "(%d, %d) matrix %d: %s vs oracle %s" % (
+                        v, q, bad[0], got[bad[0]], ref[bad[0], 3:6])
+                del b
+            finally:
+                ctx.close()
     announce("large", "c4", "plain per-matrix calls")
     res = torch.empty((len(ref), 3), dtype=torch.int64, device=dev)
     for k, (d, nn) in enumerate(items):
