@@ -201,6 +201,34 @@ def large_section(L, h, dev, names, reps, golden):
         t_p = sum(e[0].elapsed_time(e[1]) for e in ev) / reps * 1e-3
         t_m = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
         t_sm = sum(e[4].elapsed_time(e[5]) for e in ev) / reps * 1e-3
+        # the same search after ms_autotune on this matrix (a context of its own: the probe tile
+        # the tuner picks for this shape bucket), and the search + map in one call with it
+        import paper_2503_18974_amd as M
+        ctx_t = M.Context()
+        if L.ms_autotune(ctx_t.handle, d.data_ptr(), m, n, ldw, None, 0, sp):
+            raise RuntimeError("ms_autotune failed")
+        tuned_cfg = M.ms_get_config(ctx_t.handle, m, n)
+        L.ms_max_square(ctx_t.handle, d.data_ptr(), m, n, ldw, res.data_ptr(), sp)
+        torch.cuda.synchronize()
+        if tuple(res.cpu().tolist()) != got:
+            raise SystemExit("%s: tuned search result differs" % name)
+        for r in range(reps):
+            flush.fill_((r + 5) & 0xff)
+            ev[r][0].record(stream)
+            L.ms_max_square(ctx_t.handle, d.data_ptr(), m, n, ldw, res.data_ptr(), sp)
+            ev[r][1].record(stream)
+            flush.fill_((r + 6) & 0xff)
+            ev[r][2].record(stream)
+            L.ms_square_map(ctx_t.handle, d.data_ptr(), m, n, ldw, dp.data_ptr(), n,
+                            res2.data_ptr(), sp)
+            ev[r][3].record(stream)
+        torch.cuda.synchronize()
+        if tuple(res.cpu().tolist()) != got or tuple(res2.cpu().tolist()) != got \
+                or int(dp.max().item()) != g["side"]:
+            raise SystemExit("%s: tuned timed calls changed the result" % name)
+        t_pt = sum(e[0].elapsed_time(e[1]) for e in ev) / reps * 1e-3
+        t_smt = sum(e[2].elapsed_time(e[3]) for e in ev) / reps * 1e-3
+        ctx_t.close()
         # all maximal squares (enumeration of every corner with dp = S), cold as above
         ws_n = ctypes.c_size_t()
         if L.ms_all_max_squares_workspace_size(h, m, n, ctypes.byref(ws_n)):
@@ -243,13 +271,20 @@ def large_section(L, h, dev, names, reps, golden):
                            "result of ms_max_square on the same context",
                "square_map_us": t_sm * 1e6,
                "square_map_gcells_s": cells / t_sm / 1e9,
-               "square_map_frac": cells * MAP_BYTES_PER_CELL / t_sm / 1e9 / HBM_PEAK_GBS}
+               "square_map_frac": cells * MAP_BYTES_PER_CELL / t_sm / 1e9 / HBM_PEAK_GBS,
+               "tuned_probe_variant": tuned_cfg["probe_variant"],
+               "tuned_max_square_us": t_pt * 1e6,
+               "tuned_square_map_us": t_smt * 1e6,
+               "tuned_square_map_frac": cells * MAP_BYTES_PER_CELL / t_smt / 1e9 / HBM_PEAK_GBS}
         out[name] = rec
         log("large %s %dx%d S=%d: max_square %.1f us (%.0f Gcells/s), map %.1f us (%.0f GB/s, "
             "%.0f%% of peak), search + map %.1f us (%.0f%%), all %d maximal squares %.1f us"
             % (name, m, n, g["side"], t_p * 1e6, rec["max_square_gcells_s"], t_m * 1e6,
                rec["map_gbs"], 100 * rec["map_frac"], t_sm * 1e6, 100 * rec["square_map_frac"],
                count, t_a * 1e6))
+        log("large %s tuned (probe tile %d): max_square %.1f us, search + map %.1f us (%.0f%%)"
+            % (name, tuned_cfg["probe_variant"], t_pt * 1e6, t_smt * 1e6,
+               100 * rec["tuned_square_map_frac"]))
         del d, dp
         torch.cuda.empty_cache()
     del flush

@@ -71,7 +71,8 @@ typedef struct {
 
 /* Tunable launch shapes of one context (see ms_candidate / ms_set_config).
  *   probe_variant : register tile of the erosion search: 0 = 16 rows per lane, sides up to 16
- *                   certified per tile; 1 = 32 rows, 16; 2 = 32 rows, 32
+ *                   certified per tile; 1 = 32 rows, 16; 2 = 32 rows, 32; 3 = 32 rows, 64
+ *                   (fewer owned rows per tile, for images whose squares mostly exceed 32)
  *   map_cols      : columns per lane of the dp-map pass (4 or 8)
  *   map_band_rows : minimum row-band height of the dp-map pass (the band is also >= 4 S)
  * All candidates compute identical results; they differ only in speed. */

@@ -446,9 +446,11 @@ struct TileShape {
     static constexpr int HALO = KC - 1;
     static constexpr int TR = ROWS - HALO;  // owned rows per tile
     static constexpr int OWN_WORDS = NWT - 1;
+    static constexpr int HALO_RG = HALO / RPL;  // the row group where the owned rows start
+    static constexpr int HALO_R = HALO % RPL;   // and their first row in it
     static_assert(NWT == 4 || NWT == 8 || NWT == 16, "word columns per row group");
-    static_assert(HALO < RPL, "top halo must fit in the first row group");
-    static_assert(KC <= 32 && (KC & (KC - 1)) == 0, "KC power of two <= 32");
+    static_assert(HALO < ROWS / 2, "owned rows are most of the tile");
+    static_assert(KC <= 64 && (KC & (KC - 1)) == 0, "KC power of two <= 64");
 };
 
 // Within each group of NWT lanes, lane l receives lane l-1's value; the first lane of every
@@ -498,15 +500,16 @@ __device__ __forceinline__ void erode_by(const uint64_t (&E)[RPL], uint64_t (&T)
     }
 }
 
+// Owned rows: every row of the row groups past HALO_RG, and rows >= HALO_R of group HALO_RG.
 template <class TS>
 __device__ __forceinline__ bool any_owned(const uint64_t (&T)[TS::RPL], int rg, bool lane_ok) {
     uint64_t a = 0, h = 0;
 #pragma unroll
     for (int r = 0; r < TS::RPL; ++r) {
-        if (r < TS::HALO) h |= T[r];
+        if (r < TS::HALO_R) h |= T[r];
         else a |= T[r];
     }
-    const uint64_t acc = rg ? (a | h) : a;
+    const uint64_t acc = rg > TS::HALO_RG ? (a | h) : (rg == TS::HALO_RG ? a : 0ull);
     return __ballot(lane_ok && acc != 0) != 0;
 }
 
@@ -530,15 +533,15 @@ __device__ __forceinline__ bool any_in(const uint64_t (&T)[TS::RPL], int rg, boo
     uint64_t a = 0, h = 0, t = 0;
 #pragma unroll
     for (int r = 0; r < TS::RPL; ++r) {
-        if (r < TS::HALO) h |= T[r];
+        if (r < TS::HALO_R) h |= T[r];
         else a |= T[r];
-        if constexpr (DR::R != TS::HALO) {
+        if constexpr (DR::R != TS::HALO_R) {
             if (r >= DR::R) t |= T[r];
         }
     }
-    if constexpr (DR::R == TS::HALO) t = a;
+    if constexpr (DR::R == TS::HALO_R) t = a;
     // every row of the lane past row group thr counts, and in group thr the rows from the split
-    const int thr = deep ? DR::RG : 0;
+    const int thr = deep ? DR::RG : TS::HALO_RG;
     const uint64_t acc = rg > thr ? (a | h) : (rg == thr ? (deep ? t : a) : 0ull);
     return __ballot(lane_ok && acc != 0) != 0;
 }
@@ -631,7 +634,7 @@ struct SatBatch {
 // With DEEP = false a saturated tile is always SAT_FULL and pushes a lower bound instead: the
 // largest k whose erosion, continued inside the register tile past its halo, still holds an
 // owned cell (a subset of the true E_k: a real square).
-template <class TS, bool DEEP = true>
+template <class TS, bool DEEP = (4 * TS::KC <= TS::ROWS)>
 __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int64_t ty, int64_t tx, const TileSink &sink) {
     constexpr int RPL = TS::RPL;
@@ -676,10 +679,12 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
     constexpr int DMAX = TS::RPL < 16 ? TS::RPL : 16;
     constexpr int DSTEP = DMAX < TS::KC ? DMAX : TS::KC;  // divides KC: the steps end at 2 KC
     constexpr int DEEP_MAX = 2 * TS::KC;
-    int cur = 1;
+    int cur = 1, dl = 1;  // dl: the last step tried
     bool saturated = false;
     for (;;) {
-        const int d = cur < TS::KC ? cur : (DEEP ? DSTEP : DMAX);
+        // doubling, at most DMAX rows a step (a step of d reads d rows up, within one row group)
+        const int d = cur < TS::KC ? (cur < DMAX ? cur : DMAX) : (DEEP ? DSTEP : DMAX);
+        dl = d;
         if (DEEP ? (saturated && cur + d > DEEP_MAX) : (saturated && cur + DMAX > TS::ROWS)) break;
         erode_by<RPL, TS::NWT>(E, T, d, rg, wl);
         if (DEEP ? !any_in<TS>(T, rg, lane_ok, saturated) : !any_owned<TS>(T, rg, lane_ok)) break;
@@ -693,11 +698,11 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
         }
     }
     const bool full = saturated && (!DEEP || cur >= DEEP_MAX);
-    // the side (over the deep rows when saturated) is in [cur, 2 cur - 1] (unsaturated), in
+    // the side (over the deep rows when saturated) is in [cur, cur + dl - 1] (unsaturated), in
     // [cur, cur + DSTEP - 1] (saturated), or at least 2 KC (full)
-    if (!saturated && 2 * cur - 1 < best) return 2 * cur - 1;
+    if (!saturated && cur + dl - 1 < best) return cur + dl - 1;
     const int d0 = DEEP ? (full ? 0 : DSTEP >> 1) : DMAX >> 1;
-    for (int d = saturated ? d0 : cur >> 1; d >= 1; d >>= 1) {
+    for (int d = saturated ? d0 : dl >> 1; d >= 1; d >>= 1) {
         erode_by<RPL, TS::NWT>(E, T, d, rg, wl);
         if (DEEP ? any_in<TS>(T, rg, lane_ok, saturated) : any_owned<TS>(T, rg, lane_ok)) {
 #pragma unroll
@@ -714,8 +719,9 @@ __device__ __forceinline__ int32_t tile_search(const uint64_t *__restrict__ bits
 #pragma unroll
         for (int r = RPL - 1; r >= 0; --r) {
             using DR = DeepRows<TS>;
-            const bool take = DEEP && saturated ? (rg > DR::RG || (r >= DR::R && rg == DR::RG))
-                                                : (rg || r >= TS::HALO);
+            const bool take = DEEP && saturated
+                                  ? (rg > DR::RG || (r >= DR::R && rg == DR::RG))
+                                  : (rg > TS::HALO_RG || (r >= TS::HALO_R && rg == TS::HALO_RG));
             const int64_t row = tile_r0 + rg * RPL + r;
             if (take && E[r]) pos = row * n + wlane * 64 + (__ffsll((long long)E[r]) - 1);
         }

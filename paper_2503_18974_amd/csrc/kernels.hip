@@ -1088,14 +1088,18 @@ namespace mshost {
 using TS0 = msk::TileShape<16, 16>;
 using TS1 = msk::TileShape<32, 16>;
 using TS2 = msk::TileShape<32, 32>;
+// certifies side 64 (its halo spans two row groups; 65 owned rows): for images whose squares
+// are mostly between 32 and 64 (blobs), where the 32-certified tile saturates nearly everywhere
+using TS3 = msk::TileShape<32, 64>;
 
-const ProbeVariant PROBE_VARIANTS[NUM_PROBE_VARIANTS] = {{16, 16}, {32, 16}, {32, 32}};
+const ProbeVariant PROBE_VARIANTS[NUM_PROBE_VARIANTS] = {{16, 16}, {32, 16}, {32, 32}, {32, 64}};
 
 int64_t probe_tile_rows(int variant) {
     switch (variant) {
     case 0: return TS0::TR;
     case 1: return TS1::TR;
-    default: return TS2::TR;
+    case 2: return TS2::TR;
+    default: return TS3::TR;
     }
 }
 
@@ -1143,7 +1147,7 @@ int64_t max_probe_blocks(int num_cus) { return (int64_t)num_cus * 8; }
 
 int64_t max_probe_tiles(int64_t m, int64_t n) {
     const int64_t nw = cdiv(std::max<int64_t>(n, 1), 64);
-    const int64_t rows = std::min<int64_t>({TS0::TR, TS1::TR, TS2::TR});
+    const int64_t rows = std::min<int64_t>({TS0::TR, TS1::TR, TS2::TR, TS3::TR});
     return cdiv(std::max<int64_t>(m, 1), rows) * cdiv(nw, (int64_t)PROBE_TILE_WORDS);
 }
 
@@ -1157,8 +1161,11 @@ hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *
     case 1:
         return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
                                          box_rec, out);
-    default:
+    case 2:
         return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
+                                        box_rec, out);
+    default:
+        return launch_max_square_t<TS3>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
                                         box_rec, out);
     }
 }
@@ -1275,6 +1282,7 @@ BatchLayout batch_layout(int variant, int q, const ms_matrix *h_mats, int64_t co
                             : std::max<uint64_t>({(uint64_t)msk::tile_count<TS0>(d.m, d.n),
                                                   (uint64_t)msk::tile_count<TS1>(d.m, d.n),
                                                   (uint64_t)msk::tile_count<TS2>(d.m, d.n),
+                                                  (uint64_t)msk::tile_count<TS3>(d.m, d.n),
                                                   (uint64_t)msk::tile_count<msk::TSN>(d.m, d.n)});
             maxn = std::max<int64_t>(maxn, d.n);
             mix += msk::shape_mix((uint64_t)i, (uint64_t)d.m, (uint64_t)d.n,
@@ -1284,7 +1292,8 @@ BatchLayout batch_layout(int variant, int q, const ms_matrix *h_mats, int64_t co
     switch (variant) {
     case 0: pass(TS0{}); break;
     case 1: pass(TS1{}); break;
-    default: pass(TS2{}); break;
+    case 2: pass(TS2{}); break;
+    default: pass(TS3{}); break;
     }
     L.total_tiles = tiles;
     L.max_nwords = cdiv(maxn, 64);
@@ -1345,7 +1354,8 @@ hipError_t launch_batched(const LaunchEnv &env, int variant, const ms_matrix *d_
     switch (variant) {
     case 0: return launch_batched_t<TS0>(env, d_mats, count, out, w, L);
     case 1: return launch_batched_t<TS1>(env, d_mats, count, out, w, L);
-    default: return launch_batched_t<TS2>(env, d_mats, count, out, w, L);
+    case 2: return launch_batched_t<TS2>(env, d_mats, count, out, w, L);
+    default: return launch_batched_t<TS3>(env, d_mats, count, out, w, L);
     }
 }
 

@@ -33,7 +33,7 @@ struct ProbeVariant {
     int rpl;  // rows per lane
     int kc;   // largest side certified by the tile's halo
 };
-constexpr int NUM_PROBE_VARIANTS = 3;
+constexpr int NUM_PROBE_VARIANTS = 4;
 extern const ProbeVariant PROBE_VARIANTS[NUM_PROBE_VARIANTS];
 
 int64_t probe_tile_rows(int variant);           // owned rows per tile

@@ -69,7 +69,7 @@ def test_autotune_batched(dev, tmp_path):
     M.ms_autotune_save(ctx.handle, path)
     batched = [line.split() for line in open(path) if line.startswith("batched ")]
     assert len(batched) == 1 and len(batched[0]) == 3          # variant and tile-width weight
-    assert int(batched[0][1]) in (0, 1, 2) and int(batched[0][2]) in (4, 0, 2, 8)
+    assert int(batched[0][1]) in (0, 1, 2, 3) and int(batched[0][2]) in (4, 0, 2, 8)
     ctx2 = M.Context()
     M.ms_autotune_load(ctx2.handle, path)
     b2 = M.Batch(items, ctx=ctx2)

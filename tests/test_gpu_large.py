@@ -93,7 +93,7 @@ def test_c4_batched_full(dev, tmp_path):
     # every launch shape the batched autotuner can choose (probe tile x tile-width weight),
     # each forced through a loaded tuning table on a fresh context, run twice (the second
     # call is replayed from a captured graph)
-    for v in range(3):
+    for v in range(4):
         for q in (4, 0, 2, 8):
             announce("large", "c4", "batched candidate", v, q)
             table = os.path.join(tmp_path, "c4_%d_%d.txt" % (v, q))

@@ -106,7 +106,7 @@ def test_blob(dev):
     assert_same(a, dev)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("shape,sigma,pct,seed", [((1500, 4100), 9.0, 50.0, 21),
                                                   ((2200, 2900), 12.0, 45.0, 22)])
 def test_blob_grouped_resolve(dev, variant, shape, sigma, pct, seed):
@@ -228,7 +228,7 @@ def test_equal_squares_first_corner(dev, layout):
 # Probe tiles per variant: (owned rows TR, certified side KC).  The owned rows of a tile at
 # offset >= KC from its first row (the "deep" rows) are exact inside the probe's register tile
 # for sides up to 2 KC; the resolve pass then finishes only the first KC rows of the tile.
-PROBE_TILES = {0: (49, 16), 1: (113, 16), 2: (97, 32)}
+PROBE_TILES = {0: (49, 16), 1: (113, 16), 2: (97, 32), 3: (65, 64)}
 
 
 def _deep_rows_cases(TR, KC):
@@ -254,7 +254,7 @@ def _deep_rows_cases(TR, KC):
     ]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_deep_rows_of_saturated_tiles(dev, variant):
     """Saturated tiles whose deep rows the probe finishes: ties between the first rows and the
     deep rows, sides at 2 KC - 1, 2 KC and beyond, squares reaching into the tile above, a
@@ -273,6 +273,7 @@ def test_deep_rows_of_saturated_tiles(dev, variant):
             for q, (off, side) in enumerate(squares):
                 r1 = ta + off
                 c1 = 1100 + q * 400  # the square's right column
+                side = min(side, r1 + 1)  # the 64-certified tile's rows: keep it in the matrix
                 a[r1 - side + 1:r1 + 1, c1 - side + 1:c1 + 1] = 1
             assert_same(a, dev, ctx=ctx)
     finally:
