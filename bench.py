@@ -6,9 +6,9 @@ Workload (the paper's experimental shape, Section 4): 45 square Bernoulli matric
 resident in HBM before timing.  One step = for every matrix, the plain one-launch-per-matrix
 path: bit-pack (ms_pack_u8), largest square (ms_max_square: erosion search and exact pass),
 and the int32 dp map (ms_square_map_from_max).  value = total cells per second over the
-timed steps, with the matrices dealt over four streams (one context each) and the step's
-launches recorded once as a HIP graph and replayed; the single-stream eager loop is reported
-beside it.
+timed steps, with the matrices dealt over four streams (one context each, each stream on a
+hardware queue of its own) and each stream's launches recorded once as a HIP graph and replayed
+on it; the single-stream eager loop and the four streams' eager launches are reported beside it.
 
 Also reported: the dp-map kernel's achieved algorithmic bandwidth (HIP events around every
 map launch inside the timed steps) against the 8 TB/s HBM peak; the batched entry point over
@@ -634,7 +634,14 @@ def main():
     ap.add_argument("--no-rect", action="store_true")
     ap.add_argument("--no-cube", action="store_true")
     ap.add_argument("--c4-reps", type=int, default=10)
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
     args = ap.parse_args()
+    # Hardware queues per process (read once, when HIP starts): with HIP's default of four, two
+    # of the grid step's four streams share a queue and run in turn (440 against 590 Gcells/s
+    # with eight queues, each stream's launches eager or replayed from its own graph).
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -781,14 +788,17 @@ def main():
             load[s] += calls[i][0] ** 2
             lanes[s].append(calls[i])
 
+        def lane(s):
+            hs, ss = ctxs[s].handle, streams[s].cuda_stream
+            for (n, pa, pb, ldw, pdp, pres) in lanes[s]:
+                if (L.ms_pack_u8(hs, pa, n, n, n, pb, ldw, ss)
+                        or L.ms_max_square(hs, pb, n, n, ldw, pres, ss)
+                        or L.ms_square_map_from_max(hs, pb, n, n, ldw, pres, pdp, n, ss)):
+                    raise RuntimeError("per-matrix call failed on stream %d" % s)
+
         def mstep():
             for s in range(nst):
-                hs, ss = ctxs[s].handle, streams[s].cuda_stream
-                for (n, pa, pb, ldw, pdp, pres) in lanes[s]:
-                    if (L.ms_pack_u8(hs, pa, n, n, n, pb, ldw, ss)
-                            or L.ms_max_square(hs, pb, n, n, ldw, pres, ss)
-                            or L.ms_square_map_from_max(hs, pb, n, n, ldw, pres, pdp, n, ss)):
-                        raise RuntimeError("per-matrix call failed on stream %d" % s)
+                lane(s)
 
         RES.fill_(-9)
         torch.cuda.synchronize()
@@ -802,34 +812,43 @@ def main():
             mstep()
         torch.cuda.synchronize()
         t_ms = (time.perf_counter() - t0) / args.steps
-        multi = {"streams": nst, "gcells_s": cells / t_ms / 1e9, "ms_per_step": t_ms * 1e3}
+        multi = {"streams": nst, "gcells_s": cells / t_ms / 1e9, "ms_per_step": t_ms * 1e3,
+                 "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))}
         log("%d streams: %.3f ms per step, %.1f Gcells/s" % (nst, t_ms * 1e3, multi["gcells_s"]))
         if not args.no_graph:
-            # the same fan-out recorded once: the side streams fork from and join back to the
-            # capturing stream, so the graph holds one independent branch per stream
-            gm = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(gm):
-                cs = torch.cuda.current_stream()
-                for st in streams:
-                    st.wait_stream(cs)
-                mstep()
-                for st in streams:
-                    cs.wait_stream(st)
+            # each stream's launches recorded once as a graph of its own and replayed on that
+            # stream: four independent chains, one submission per stream per step
+            graphs = []
+            for s in range(nst):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=streams[s]):
+                    lane(s)
+                graphs.append(g)
+
+            def gstep():
+                for s in range(nst):
+                    with torch.cuda.stream(streams[s]):
+                        graphs[s].replay()
+
             RES.fill_(-9)
-            gm.replay()
+            torch.cuda.synchronize()
+            gstep()
             torch.cuda.synchronize()
             if not np.array_equal(RES.cpu().numpy(), res):
                 raise SystemExit("graph-replayed multi-stream step gives different results")
+            for _ in range(max(args.warmup, 1)):
+                gstep()
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(args.steps):
-                gm.replay()
+                gstep()
             torch.cuda.synchronize()
             t_gm = (time.perf_counter() - t0) / args.steps
             multi["graph_gcells_s"] = cells / t_gm / 1e9
             multi["graph_ms_per_step"] = t_gm * 1e3
-            log("%d streams, graph-replayed: %.3f ms per step, %.1f Gcells/s"
+            log("%d streams, a graph per stream replayed: %.3f ms per step, %.1f Gcells/s"
                 % (nst, t_gm * 1e3, multi["graph_gcells_s"]))
-            del gm
+            del graphs
         for c in ctxs:
             c.close()
 
@@ -886,16 +905,18 @@ def main():
         extra["serving"] = serve_section(dev, (1000, 5000, 20000), args.serve_requests,
                                          args.serve_pool, args.serve_budget_gib)
 
-    # the headline: the per-matrix calls fanned out over several streams and replayed as one
-    # HIP graph when that ran, else the single-stream eager loop
+    # the headline: the per-matrix calls fanned out over several streams, each stream's replayed
+    # from its own HIP graph when that ran, else launched eagerly; with one stream, the eager loop
     submission = "one stream, eager launches"
     head_value, head_ms = value, ms_per_step
     if multi is not None and "graph_gcells_s" in multi:
-        submission = ("%d streams (one context each), the per-matrix launches recorded once as a "
-                      "HIP graph and replayed" % multi["streams"])
+        submission = ("%d streams (one context each, %d hardware queues), each stream's "
+                      "per-matrix launches recorded once as its own HIP graph and replayed on it"
+                      % (multi["streams"], multi["hw_queues"]))
         head_value, head_ms = multi["graph_gcells_s"], multi["graph_ms_per_step"]
     elif multi is not None:
-        submission = "%d streams (one context each), eager launches" % multi["streams"]
+        submission = ("%d streams (one context each, %d hardware queues), eager launches"
+                      % (multi["streams"], multi["hw_queues"]))
         head_value, head_ms = multi["gcells_s"], multi["ms_per_step"]
     out = {
         "metric": METRIC,

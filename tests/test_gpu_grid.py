@@ -92,9 +92,9 @@ def test_grid_single_stream_eager(dev, grid):
 
 
 def test_grid_four_streams_graph_replay(dev, grid):
-    """The headline submission: largest matrices first to the least-loaded of four streams,
-    recorded once as a graph (side streams fork from and join the capturing stream), replayed
-    twice with the outputs cleared in between."""
+    """Largest matrices first to the least-loaded of four streams, recorded once as one graph
+    (side streams fork from and join the capturing stream), replayed twice with the outputs
+    cleared in between."""
     import torch
     announce("grid", "four streams, graph")
     L = M.lib()
@@ -131,6 +131,51 @@ def test_grid_four_streams_graph_replay(dev, grid):
             g.replay()
             check_all(grid, "graph replay %d" % rep)
         del g
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_grid_graph_per_stream(dev, grid):
+    """The headline submission: the same four lanes, each recorded as a graph of its own on its
+    stream and replayed there; three replays, the outputs cleared and an eager step run
+    between them."""
+    import torch
+    announce("grid", "a graph per stream")
+    L = M.lib()
+    calls = calls_of(grid)
+    nst = 4
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
+    ctxs = [M.Context() for _ in range(nst)]
+    try:
+        load = [0] * nst
+        lanes = [[] for _ in range(nst)]
+        for i in sorted(range(len(calls)), key=lambda k: -calls[k][0]):
+            s = min(range(nst), key=lambda k: load[k])
+            load[s] += calls[i][0] ** 2
+            lanes[s].append(calls[i])
+        for s in range(nst):  # eager once: every context's scratch allocated outside a capture
+            run_calls(L, ctxs[s].handle, streams[s].cuda_stream, lanes[s])
+        torch.cuda.synchronize()
+        graphs = []
+        for s in range(nst):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=streams[s]):
+                run_calls(L, ctxs[s].handle, streams[s].cuda_stream, lanes[s])
+            graphs.append(g)
+        for rep in range(3):
+            reset(grid)
+            torch.cuda.synchronize()
+            for s in range(nst):
+                with torch.cuda.stream(streams[s]):
+                    graphs[s].replay()
+            check_all(grid, "graph per stream, replay %d" % rep)
+            reset(grid)
+            torch.cuda.synchronize()
+            for s in range(nst):
+                run_calls(L, ctxs[s].handle, streams[s].cuda_stream, lanes[s])
+            check_all(grid, "eager between replays %d" % rep)
+        del graphs
     finally:
         for c in ctxs:
             c.close()
