@@ -1228,7 +1228,8 @@ template <class TS, int NW>
 __device__ void resolve_tile_block(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
                                    int64_t ldw, int64_t ty, int64_t tx, int64_t ntx,
                                    const uint8_t *__restrict__ sat, unsigned long long *key,
-                                   uint32_t *serial_flag, int32_t *bounds, ResolveLds &L) {
+                                   uint32_t *serial_flag, int32_t *bounds, ResolveLds &L,
+                                   uint32_t *serial_count = nullptr) {
     constexpr int64_t OWN_COLS = 64 * TS::OWN_WORDS;
     const int lane = __lane_id();
     const int wv = uniform((int32_t)(threadIdx.x / WAVE));  // wave-uniform: keep it scalar
@@ -1271,8 +1272,9 @@ __device__ void resolve_tile_block(const uint64_t *__restrict__ bits, int64_t m,
     const int64_t nwords = (n + 63) >> 6;
     for (;;) {
         U = U < ucap ? U : ucap;
-        if (!fits(U)) {  // the serial pass finishes the matrix
-            if (wv == 0 && lane == 0) atomicOr(serial_flag, 1u);
+        if (!fits(U)) {  // the serial pass finishes the matrix (serial_count: matrices flagged)
+            if (wv == 0 && lane == 0 && atomicOr(serial_flag, 1u) == 0u && serial_count)
+                atomicAdd(serial_count, 1u);
             return;
         }
         const int64_t w0 = xa - U > 0 ? ((xa - U) >> 6) : 0;

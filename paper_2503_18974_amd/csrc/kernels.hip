@@ -820,10 +820,11 @@ __device__ void batch_result(const ms_matrix *__restrict__ mats, int64_t i,
 //  * An inconsistent batch (the probe refused it): every result -1.
 //  * No saturated tile (the common case): the keys are final; the grid writes the results,
 //    one matrix per thread, at once.
-//  * Otherwise the waves finish the saturated tiles of every matrix (resolve_tile), blocks count
-//    themselves done (a completion count, nothing waits), and the last block writes every
-//    result; its first wave runs the serial pass for the matrices whose square was too wide for
-//    the resolve window.
+//  * Otherwise the saturated tiles of every matrix are finished, each by a block of four waves
+//    sharing its height scan (resolve_tile_block) when there are at most as many as blocks,
+//    else each by one wave (resolve_tile); blocks count themselves done (a completion count,
+//    nothing waits), and the last block writes every result; its first wave runs the serial
+//    pass for the matrices whose square was too wide for the resolve window.
 template <class TS>
 __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restrict__ mats,
                                                       unsigned long long *__restrict__ keys,
@@ -836,6 +837,7 @@ __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restric
                                                       uint64_t total, int32_t *serial_state,
                                                       int64_t state_words, ms_square *out,
                                                       int q) {
+    __shared__ ResolveLds L;
     const int lane = __lane_id();
     const BatchIndex ix{local, off, count, nblk};
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -844,7 +846,8 @@ __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restric
         for (int64_t i = tid; i < count; i += nthr) out[i] = ms_square{-1, -1, -1};
         return;
     }
-    if (uniform((int32_t)load_relaxed_u32(&ctr->nsat)) == 0) {
+    const uint32_t nsat = (uint32_t)uniform((int32_t)load_relaxed_u32(&ctr->nsat));
+    if (nsat == 0) {
         for (int64_t i = tid; i < count; i += nthr) {
             const ms_matrix d = mats[i];
             write_result(load_relaxed(keys + i), d.n, out + i);
@@ -853,7 +856,39 @@ __global__ __launch_bounds__(256) void k_batch_finish(const ms_matrix *__restric
     }
     const uint64_t wave = (uint64_t)wave_index();
     const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) / WAVE;
-    for (uint64_t base = wave; base < total; base += 64 * nwave) {
+    const uint64_t nb = gridDim.x;
+    // Few saturated tiles (a large square or a blob in a small batch): one block per tile, its
+    // four waves sharing the tile's height scan, tiles dealt to blocks by index modulo the grid;
+    // every wave of a block reads the same bytes, so the block agrees on its sequence of tiles.
+    for (uint64_t base = blockIdx.x; nsat <= nb && base < total; base += 64 * nb) {
+        const uint64_t g = base + (uint64_t)lane * nb;
+        uint64_t b = __ballot(g < total && sat[g] != 0);
+        while (b) {
+            const int l = __ffsll((long long)b) - 1;
+            b &= b - 1;
+            const uint64_t item = base + (uint64_t)l * nb;
+            const int64_t mi = ix.find(item);
+            const ms_matrix d = mats[mi];
+            const int64_t nwords = (d.n + 63) >> 6;
+            const uint64_t st = ix.start(mi);
+            const int64_t t = (int64_t)(item - st);
+            if (uniform((int32_t)narrow_tiles<TS>(d.m, d.n, q))) {
+                const int64_t ntx = (nwords + TSN::OWN_WORDS - 1) / TSN::OWN_WORDS;
+                const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
+                resolve_tile_block<TSN, RESOLVE_WAVES>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx,
+                                                       sat + st, keys + mi, flags + mi, nullptr,
+                                                       L, &ctr->nserial);
+            } else {
+                const int64_t ntx = (nwords + TS::OWN_WORDS - 1) / TS::OWN_WORDS;
+                const int64_t ty = udiv(t, ntx), tx = t - ty * ntx;
+                resolve_tile_block<TS, RESOLVE_WAVES>(d.bits, d.m, d.n, d.ld_words, ty, tx, ntx,
+                                                      sat + st, keys + mi, flags + mi, nullptr,
+                                                      L, &ctr->nserial);
+            }
+        }
+    }
+    // many: one wave per tile
+    for (uint64_t base = wave; nsat > nb && base < total; base += 64 * nwave) {
         const uint64_t g = base + (uint64_t)lane * nwave;
         uint64_t b = __ballot(g < total && sat[g] != 0);
         while (b) {
@@ -1338,10 +1373,11 @@ static hipError_t launch_batched_t(const LaunchEnv &env, const ms_matrix *mats, 
                        env.stream, mats, keys, local, offs, count, L.nblk, ctr, sat,
                        (uint64_t)L.total_tiles, L.narrow_q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // results, and the saturated tiles first if any (one launch)
+    // results, and the saturated tiles first if any (one launch): a block per tile up to four
+    // per CU, so that a few saturated tiles get a block each
     const int64_t fblocks = std::max<int64_t>(
-        1, std::min<int64_t>(std::max<int64_t>(cdiv((int64_t)L.total_tiles, 8), cdiv(count, 256)),
-                             (int64_t)env.num_cus * 2));
+        1, std::min<int64_t>(std::max<int64_t>((int64_t)L.total_tiles, cdiv(count, 256)),
+                             (int64_t)env.num_cus * 4));
     hipLaunchKernelGGL(msk::k_batch_finish<TS>, dim3((unsigned)fblocks), dim3(256), 0,
                        env.stream, mats, keys, local, offs, count, L.nblk, flags, ctr, sat,
                        (uint64_t)L.total_tiles, state, L.max_nwords, out, L.narrow_q);

@@ -1,5 +1,7 @@
 """Batched entry point: every result equals the single-matrix call and the oracle, under mixed
 shapes, empty matrices, duplicates and shuffled order."""
+import os
+
 import numpy as np
 import pytest
 
@@ -239,3 +241,54 @@ def test_mismatched_device_descriptors_fail_every_result(dev):
                                  ws.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
     assert st == 0
     assert [tuple(r) for r in out.cpu().tolist()] == [oracle.max_square(a), oracle.max_square(b)]
+
+
+# the narrow tile of the batched path: 241 owned rows, certified side 16
+NARROW_TILE = (241, 16)
+
+
+def _deep_row_mats(TR, KC, seed, n, cols):
+    """One matrix per deep-row case (tile row 1 of a TR-row tile, squares with their right
+    columns at `cols`), 0.5-dense noise around them."""
+    from test_gpu_parity import _deep_rows_cases
+    out = []
+    for k, (name, squares) in enumerate(_deep_rows_cases(TR, KC)):
+        rng = np.random.default_rng([seed, k])
+        m = 3 * TR + 7
+        a = (rng.random((m, n)) < 0.5).astype(np.uint8)
+        for q, (off, side) in enumerate(squares):
+            r1 = TR + off
+            c1 = cols[q]
+            side = min(side, r1 + 1, c1 + 1)
+            a[r1 - side + 1:r1 + 1, c1 - side + 1:c1 + 1] = 1
+        out.append((name, a))
+    return out
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_batched_deep_rows(dev, variant, tmp_path):
+    """The deep-row cases of the single-matrix search, every one in one batch: wide matrices on
+    the variant's own tile (never narrow), and 150-column matrices on the narrow tile (the
+    default tile-width rule picks it there), each result against the oracle."""
+    import torch
+    from test_gpu_parity import PROBE_TILES
+    TR, KC = PROBE_TILES[variant]
+    cases = _deep_row_mats(TR, KC, [variant, 21], 2100, (1100, 1500))
+    cases += _deep_row_mats(*NARROW_TILE, [variant, 22], 150, (60, 120))
+    for q in (0, 4):
+        announce("batched deep rows", variant, q)
+        table = os.path.join(tmp_path, "deep_%d_%d.txt" % (variant, q))
+        with open(table, "w") as f:
+            f.write("batched %d %d\n" % (variant, q))
+        ctx = M.Context()
+        try:
+            M.ms_autotune_load(ctx.handle, table)
+            items = [(to_dev_bits(oracle.pack(a), dev), a.shape[1]) for _, a in cases]
+            b = M.Batch(items, ctx=ctx)
+            got = b.run().cpu().tolist()
+            torch.cuda.synchronize()
+            for (name, a), g in zip(cases, got):
+                assert tuple(g) == oracle.max_square(a), (variant, q, name, a.shape, g)
+            del b
+        finally:
+            ctx.close()
