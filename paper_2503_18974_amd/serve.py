@@ -421,6 +421,19 @@ class GpuExecutor:
                 "event": torch.cuda.Event(),
                 "busy": False,
             })
+        # Size every slot context's scratch for the largest admissible request now (one search
+        # over an all-zeros max_n x max_n matrix): a context grows its scratch on demand, and
+        # growing waits for the whole device, which would land in some request's latency.
+        zero = torch.zeros((int(max_n), (int(max_n) + 63) // 64), dtype=torch.int64,
+                           device=self.dev)
+        res = torch.empty(3, dtype=torch.int64, device=self.dev)
+        for slot in self.slots:
+            rc = self.L.ms_max_square(slot["ctx"].handle, zero.data_ptr(), int(max_n), int(max_n),
+                                      zero.stride(0), res.data_ptr(), slot["stream"].cuda_stream)
+            if rc:
+                raise RuntimeError("ms_max_square failed while sizing a slot: %d" % rc)
+        torch.cuda.synchronize(self.dev)
+        del zero, res
 
     def host_bits(self, bits):
         """Pinned host copy of a packed matrix (int64 view), for asynchronous uploads."""
