@@ -177,7 +177,7 @@ int bucket_of(int64_t m, int64_t n) {
 // columns per lane: 8 (one entering-run computation per 8 cells) is faster for one map alone
 // (2000^2: 11.2 instead of 12.5 us) but its 32-byte lane strides make each store instruction
 // touch twice the cache lines, and with maps of several streams in flight the grid step drops
-// (541 against 568 Gcells/s).
+// (567 against 588 Gcells/s with four streams, each on its own hardware queue).
 constexpr int64_t LARGE_CELLS = int64_t(1) << 26;
 constexpr int64_t SMALL_CELLS = int64_t(1) << 24;
 
