@@ -205,9 +205,11 @@ bool config_valid(const ms_config &cfg) {
 ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     const int64_t nwords = std::max<int64_t>(1, cdiv(n, 64));
     const int64_t tiles = mshost::max_probe_tiles(m, n);
+    const mshost::LaunchEnv env{c->num_cus, stream};
     if (c->scratch && c->state_words >= nwords && c->sat_bytes >= tiles) {
         if (c->dirty) {
-            if (hipMemsetAsync(c->scratch, 0, sizeof(mshost::ScratchHeader), stream) != hipSuccess)
+            if (mshost::launch_zero_header(env, c->scratch, sizeof(mshost::ScratchHeader)) !=
+                hipSuccess)
                 return MS_ERR_HIP;
             c->dirty = false;
         }
@@ -230,7 +232,10 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return hip_status(e);
-    if (hipMemset(p, 0, sizeof(mshost::ScratchHeader)) != hipSuccess) {
+    // the header is zeroed on the caller's stream, ahead of the search launched there next (a
+    // memset on the null stream may still be pending when a non-blocking stream runs the probe,
+    // and would then erase keys it pushed)
+    if (mshost::launch_zero_header(env, p, sizeof(mshost::ScratchHeader)) != hipSuccess) {
         (void)hipFree(p);
         return MS_ERR_HIP;
     }
@@ -573,23 +578,25 @@ ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64
     std::lock_guard<std::mutex> lk(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return MS_ERR_HIP;
     hipStream_t st = (hipStream_t)stream;
+    mshost::LaunchEnv env{c->num_cus, st};
     if (!c->rect_scratch) {
         const size_t bytes = sizeof(mshost::RectScratch) +
                              (size_t)mshost::rect_max_blocks(c->num_cus) * sizeof(mshost::RectRecord);
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) return hip_status(e);
-        if (hipMemset(p, 0, sizeof(mshost::RectScratch)) != hipSuccess) {
+        // zeroed on the call's stream, ahead of the launch there (see ensure_scratch)
+        if (mshost::launch_zero_header(env, p, sizeof(mshost::RectScratch)) != hipSuccess) {
             (void)hipFree(p);
             return MS_ERR_HIP;
         }
         c->rect_scratch = p;
     } else if (c->rect_dirty) {
-        if (hipMemsetAsync(c->rect_scratch, 0, sizeof(mshost::RectScratch), st) != hipSuccess)
+        if (mshost::launch_zero_header(env, c->rect_scratch, sizeof(mshost::RectScratch)) !=
+            hipSuccess)
             return MS_ERR_HIP;
     }
     c->rect_dirty = false;
-    mshost::LaunchEnv env{c->num_cus, st};
     hipError_t e = mshost::launch_max_rect(env, d_bits, m, n, ld_words,
                                            static_cast<mshost::RectScratch *>(c->rect_scratch),
                                            d_out);

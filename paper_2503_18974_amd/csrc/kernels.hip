@@ -560,6 +560,12 @@ __global__ void k_clear_header(mshost::ScratchHeader *hdr) {
     if (threadIdx.x < W) reinterpret_cast<uint32_t *>(hdr)[threadIdx.x] = 0u;
 }
 
+// Zero `words` 32-bit words (a context header) on the caller's stream: ordered before the
+// launches that follow it there, which a memset on the null stream is not.
+__global__ void k_zero_words(uint32_t *p, int words) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------------------------- batched
 struct BatchCounters {
     uint32_t error;    // bit 1: the device tile total disagrees with the host's
@@ -1230,6 +1236,12 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
                            box, min_items);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_header(const LaunchEnv &env, void *p, size_t bytes) {
+    hipLaunchKernelGGL(msk::k_zero_words, dim3(1), dim3(64), 0, env.stream,
+                       static_cast<uint32_t *>(p), (int)(bytes / sizeof(uint32_t)));
     return hipGetLastError();
 }
 

@@ -80,6 +80,8 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const MapRegions *regions = nullptr);
 
 // Write a constant result (empty matrices).
+// Zero a context header of `bytes` (a multiple of 4, at most 256) on env.stream.
+hipError_t launch_zero_header(const LaunchEnv &env, void *p, size_t bytes);
 hipError_t launch_write_result(const LaunchEnv &env, ms_square *out, ScratchHeader *hdr,
                                int64_t count);
 

@@ -179,3 +179,33 @@ def test_grid_graph_per_stream(dev, grid):
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_grid_streams_scratch_grows_mid_run(dev, grid):
+    """Fresh contexts on four streams, each stream's smallest matrices first: every context
+    grows its scratch partway through the run while the other streams are busy.  The grown
+    scratch's header must be zeroed in order on the call's own stream; zeroed on the null
+    stream, it was once cleared after the probe had pushed its keys (right side, later corner)."""
+    import torch
+    announce("grid", "four streams, scratch growing mid-run")
+    L = M.lib()
+    calls = calls_of(grid)
+    nst = 4
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
+    ctxs = [M.Context() for _ in range(nst)]
+    try:
+        load = [0] * nst
+        lanes = [[] for _ in range(nst)]
+        for i in sorted(range(len(calls)), key=lambda k: -calls[k][0]):
+            s = min(range(nst), key=lambda k: load[k])
+            load[s] += calls[i][0] ** 2
+            lanes[s].append(calls[i])
+        lanes = [lst[::-1] for lst in lanes]  # smallest first: the scratch grows as sizes rise
+        reset(grid)
+        torch.cuda.synchronize()
+        for s in range(nst):
+            run_calls(L, ctxs[s].handle, streams[s].cuda_stream, lanes[s])
+        check_all(grid, "scratch growing mid-run")
+    finally:
+        for c in ctxs:
+            c.close()
