@@ -589,9 +589,12 @@ __host__ __device__ __forceinline__ int64_t tile_count(int64_t m, int64_t n) {
 }
 
 // The tile width of one matrix: narrow when 4 x its narrow-tile work is below q x its wide-tile
-// work.  q = NARROW_DEFAULT compares the two works as they are; the batched autotuner also tries
-// 0 (never narrow), 2 and 8 (narrow when its work is below half, or twice, the wide tile's).
-constexpr int NARROW_DEFAULT = 4;
+// work.  The default, q = 2, takes the narrow tile only where its work is below half the wide
+// tile's: a narrow tile spends a quarter of its words on the halo and measures slower than its
+// work alone says (the 45-matrix grid in one batch: 90 us with q = 2, 152 us with q = 4; the
+// 10000-matrix batch 0.447 against 0.483 ms).  The batched autotuner also tries 0 (never
+// narrow), 4 (the two works as they are) and 8 (narrow up to twice the wide tile's work).
+constexpr int NARROW_DEFAULT = 2;
 template <class TS>
 __host__ __device__ __forceinline__ bool narrow_tiles(int64_t m, int64_t n, int q) {
     return tile_count<TSN>(m, n) * TSN::RPL * 4 < tile_count<TS>(m, n) * TS::RPL * q;
@@ -1314,7 +1317,7 @@ bool narrow_weight_valid(int q) {
         if (NARROW_WEIGHTS[k] == q) return true;
     return false;
 }
-const int NARROW_WEIGHTS[NUM_NARROW_WEIGHTS] = {msk::NARROW_DEFAULT, 0, 2, 8};
+const int NARROW_WEIGHTS[NUM_NARROW_WEIGHTS] = {msk::NARROW_DEFAULT, 0, 4, 8};
 
 BatchLayout batch_layout(int variant, int q, const ms_matrix *h_mats, int64_t count) {
     BatchLayout L{};
