@@ -188,6 +188,16 @@ ms_config default_config(int64_t m, int64_t n) {
     return c;
 }
 
+// Untuned batched calls take the 49-row tile when the batch's matrices average under 2^20
+// cells, the 113-row tile otherwise: the 10000-matrix batch (0.5 Mcells a matrix) 0.426 against
+// 0.447 ms, the 45-matrix grid (11 Mcells) 187 against 90 us, 16 served requests (2.4 Mcells)
+// 146 against 122 us.
+int default_batched_variant(const ms_matrix *h_mats, int64_t count) {
+    double cells = 0;
+    for (int64_t i = 0; i < count; ++i) cells += (double)h_mats[i].m * (double)h_mats[i].n;
+    return cells < (double)count * (double)(int64_t(1) << 20) ? 0 : DEFAULT_CONFIG.probe_variant;
+}
+
 ms_config config_for(ms_ctx *c, int64_t m, int64_t n) {
     if (c->has_forced) return c->forced;
     auto it = c->tuned.find(bucket_of(m, n));
@@ -500,7 +510,7 @@ ms_status ms_max_square_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_m
     std::lock_guard<std::mutex> lk(c->mu);
     const int variant = c->has_forced ? c->forced.probe_variant
                         : c->batched_variant >= 0 ? c->batched_variant
-                                                  : DEFAULT_CONFIG.probe_variant;
+                                                  : default_batched_variant(h_mats, count);
     const int narrow = !c->has_forced && c->batched_narrow >= 0 ? c->batched_narrow
                                                                 : mshost::NARROW_WEIGHTS[0];
     const mshost::BatchLayout L = mshost::batch_layout(variant, narrow, h_mats, count);
