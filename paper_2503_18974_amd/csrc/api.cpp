@@ -919,11 +919,15 @@ ms_status ms_autotune_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_mat
     }
     mshost::LaunchEnv env{c->num_cus, st};
     int best_v = DEFAULT_CONFIG.probe_variant, best_q = mshost::NARROW_WEIGHTS[0];
-    float best_t = 1e30f;
-    // every probe variant with every tile-width weight
-    for (int v = 0; v < mshost::NUM_PROBE_VARIANTS && s == MS_OK; ++v) {
-        for (int k = 0; k < mshost::NUM_NARROW_WEIGHTS && s == MS_OK; ++k) {
-            const int q = mshost::NARROW_WEIGHTS[k];
+    // every probe variant with every tile-width weight, in two interleaved rounds, each keeping
+    // its faster round (a single round's pick moved by a few per cent from run to run)
+    constexpr int NC = mshost::NUM_PROBE_VARIANTS * mshost::NUM_NARROW_WEIGHTS;
+    float cand_t[NC];
+    for (int i = 0; i < NC; ++i) cand_t[i] = 1e30f;
+    for (int round = 0; round < 2 && s == MS_OK; ++round) {
+        for (int i = 0; i < NC && s == MS_OK; ++i) {
+            const int v = i / mshost::NUM_NARROW_WEIGHTS;
+            const int q = mshost::NARROW_WEIGHTS[i % mshost::NUM_NARROW_WEIGHTS];
             const mshost::BatchLayout L = mshost::batch_layout(v, q, h_mats, count);
             if (workspace_bytes < L.total) {
                 s = MS_ERR_WORKSPACE_TOO_SMALL;
@@ -942,13 +946,16 @@ ms_status ms_autotune_batched(ms_ctx *ctx, const ms_matrix *h_mats, const ms_mat
                 s = hip_status(e);
                 break;
             }
-            if (ms < best_t) {
-                best_t = ms;
-                best_v = v;
-                best_q = q;
-            }
+            cand_t[i] = ms < cand_t[i] ? ms : cand_t[i];
         }
     }
+    float best_t = 1e30f;
+    for (int i = 0; i < NC; ++i)
+        if (cand_t[i] < best_t) {
+            best_t = cand_t[i];
+            best_v = i / mshost::NUM_NARROW_WEIGHTS;
+            best_q = mshost::NARROW_WEIGHTS[i % mshost::NUM_NARROW_WEIGHTS];
+        }
     // leave the results of the chosen launch shape in d_out
     if (s == MS_OK) {
         const mshost::BatchLayout L = mshost::batch_layout(best_v, best_q, h_mats, count);
