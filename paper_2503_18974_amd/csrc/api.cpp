@@ -676,7 +676,6 @@ ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M,
             *f = c->pinned[0];
             return MS_OK;
         };
-        const int64_t W = cdiv(N, 64);
         // E_1: the input copied into volume 0 with its padding cleared
         if (mshost::launch_cube_pass(env, 2, d_bits, ld_words, V[0], D, M, N, 0, ctl) !=
             hipSuccess)
@@ -687,15 +686,10 @@ ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M,
             int cur = 0;
             int64_t a = 1;
             const int64_t smax = std::min(D, std::min(M, N));
-            // E_{a+b} from E_a (b <= a): one pass per axis; returns its first set voxel
+            // E_{a+b} from E_a (b <= a) in one pass; returns its first set voxel
             auto step = [&](int64_t b, int *out, uint64_t *f) -> ms_status {
-                const int x = (cur + 1) % 3, y = (cur + 2) % 3;
-                if (mshost::launch_cube_pass(env, 0, V[cur], W, V[x], D, M, N, b, ctl) !=
-                        hipSuccess ||
-                    mshost::launch_cube_pass(env, 1, V[x], W, V[y], D, M, N, b, ctl) !=
-                        hipSuccess ||
-                    mshost::launch_cube_pass(env, 2, V[y], W, V[x], D, M, N, b, ctl) !=
-                        hipSuccess)
+                const int x = (cur + 1) % 3;
+                if (mshost::launch_cube_step(env, V[cur], V[x], D, M, N, b, ctl) != hipSuccess)
                     return MS_ERR_HIP;
                 *out = x;
                 return first_of(f);

@@ -6,9 +6,10 @@
 //     E_{a+b}(z, y, x) = AND over (dz, dy, dx) in {0, b}^3 of E_a(z - dz, y - dy, x - dx),
 // and that AND is separable: one pass per axis, each ANDing the volume with itself shifted by b.
 // E_{k+1} is a subset of E_k, so the side S is found by galloping (E_1, E_2, E_4, ... until one is
-// empty) and bisecting, as in the plane case.  Each pass streams the packed volume once
-// (coalesced, HBM-bound); the x pass also reports whether the result is empty and its first set
-// voxel in (z, y, x) order, which for E_S is the reported corner.
+// empty) and bisecting, as in the plane case.  A probe step takes the eight shifted copies in one
+// pass (k_cube_step; the separable single-axis pass k_cube_pass copies the input first), which
+// also reports whether the result is empty and its first set voxel in (z, y, x) order, which for
+// E_S is the reported corner.
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -72,6 +73,57 @@ __global__ __launch_bounds__(256) void k_cube_pass(const uint64_t *__restrict__ 
     }
 }
 
+// One probe step in one pass: dst = E_{a+d} from src = E_a, the AND of the eight copies of src
+// shifted by 0 or d along each axis, taken directly (four (z, y) corner rows, each with its
+// x-shifted self) rather than as three separable passes; the rows the shifts reach are mostly
+// still in the L2 from neighbouring threads.  Voxels shifted in from outside are zeros.  Also
+// lowers ctl->first to dst's first set voxel, as the x pass does.
+__global__ __launch_bounds__(256) void k_cube_step(const uint64_t *__restrict__ src,
+                                                   uint64_t *__restrict__ dst, uint32_t D,
+                                                   uint32_t M, int64_t n, uint32_t W, uint32_t d,
+                                                   mshost::CubeControl *ctl) {
+    const uint32_t total = D * M * W;
+    const uint64_t lastmask = last_word_mask(n);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t q = d >> 6, r = d & 63;
+    unsigned long long best = ~0ull;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint32_t row = t / W, w = t - row * W;
+        const uint32_t z = row / M, y = row - z * M;
+        uint64_t acc = (z >= d && y >= d) ? ~0ull : 0ull;  // a corner outside: all zero
+        for (int c = 0; c < 4 && acc; ++c) {
+            const uint32_t dz = (c & 2) ? d : 0, dy = (c & 1) ? d : 0;
+            const uint64_t *s = src + ((int64_t)(z - dz) * M + (y - dy)) * W;
+            const uint64_t hi = w >= q ? s[w - q] : 0ull;
+            const uint64_t lo = w >= q + 1 ? s[w - q - 1] : 0ull;
+            const uint64_t o = r ? ((hi << r) | (lo >> (64 - r))) : hi;
+            acc &= s[w] & o;
+        }
+        if (w == W - 1) acc &= lastmask;
+        dst[(int64_t)row * W + w] = acc;
+        if (acc) {
+            const unsigned long long p =
+                ((unsigned long long)z * M + y) * (unsigned long long)n +
+                (unsigned long long)w * 64 + (unsigned long long)__builtin_ctzll(acc);
+            best = p < best ? p : best;
+        }
+    }
+    __shared__ unsigned long long s_min[4];
+    unsigned long long wb = best;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o2 = __shfl_xor(wb, off);
+        wb = o2 < wb ? o2 : wb;
+    }
+    if (__lane_id() == 0) s_min[threadIdx.x / WAVE] = wb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = s_min[0];
+        for (int k = 1; k < 4; ++k) b = s_min[k] < b ? s_min[k] : b;
+        if (b != ~0ull && b < load_relaxed(&ctl->first)) atomicMin(&ctl->first, b);
+    }
+}
+
 __global__ void k_cube_reset(mshost::CubeControl *ctl) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->first = ~0ull;
 }
@@ -91,6 +143,20 @@ uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k) {
     const size_t vol = (size_t)D * (size_t)M * (size_t)W * sizeof(uint64_t);
     return reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + 256 +
                                         (size_t)k * ((vol + 255) & ~(size_t)255));
+}
+
+hipError_t launch_cube_step(const LaunchEnv &env, const uint64_t *src, uint64_t *dst, int64_t D,
+                            int64_t M, int64_t n, int64_t d, CubeControl *ctl) {
+    const int64_t W = std::max<int64_t>(1, (n + 63) / 64);
+    const int64_t total = D * M * W;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256,
+                                                                   (int64_t)env.num_cus * 16));
+    hipLaunchKernelGGL(msk::k_cube_reset, dim3(1), dim3(64), 0, env.stream, ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(msk::k_cube_step, dim3((unsigned)blocks), dim3(256), 0, env.stream, src,
+                       dst, (uint32_t)D, (uint32_t)M, n, (uint32_t)W, (uint32_t)d, ctl);
+    return hipGetLastError();
 }
 
 hipError_t launch_cube_pass(const LaunchEnv &env, int axis, const uint64_t *src, int64_t lds,

@@ -164,5 +164,9 @@ uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k);
 hipError_t launch_cube_pass(const LaunchEnv &env, int axis, const uint64_t *src, int64_t lds,
                             uint64_t *dst, int64_t D, int64_t M, int64_t n, int64_t d,
                             CubeControl *ctl);
+// dst = E_{a+d} from src = E_a (both with row stride ceil(n / 64)) in one pass, resetting and then
+// setting ctl->first for dst.
+hipError_t launch_cube_step(const LaunchEnv &env, const uint64_t *src, uint64_t *dst, int64_t D,
+                            int64_t M, int64_t n, int64_t d, CubeControl *ctl);
 
 } // namespace mshost
