@@ -225,8 +225,10 @@ ms_status ms_max_rectangle(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64
  * Writes one ms_cube to d_out (device or pinned host memory): S = max c and the far corner
  * (largest z, y, x) of a largest cube, the first in (z, y, x) order; {0, -1, -1, -1} when there
  * is none.  d_workspace of ms_max_cube_workspace_size(D, M, N) bytes is caller-owned (three
- * packed volumes and a control block).  This call BLOCKS: it synchronises `stream` after each
- * probe of the side (about 2 log2 S times) to steer the search.
+ * packed volumes and a control block).  This call BLOCKS: the search over the side is steered
+ * on the device (a kernel after each probe picks the next one), and the host synchronises
+ * `stream` once per round of eight probes (about 2 log2 S probes in all) to learn whether it
+ * is done; d_out is written on the device.
  * Invalid: negative sizes, ld_words < ceil(N / 64), NULL bits (with cells), NULL d_out, NULL
  * workspace (with cells), D * M * N >= 2^44.  MS_ERR_WORKSPACE_TOO_SMALL as usual;
  * MS_ERR_UNSUPPORTED when D * M * ceil(N / 64) >= 2^32.

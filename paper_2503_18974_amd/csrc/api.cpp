@@ -660,79 +660,44 @@ ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M,
         c->pinned = static_cast<uint64_t *>(p);
     }
     hipStream_t st = (hipStream_t)stream;
-    ms_cube res{0, -1, -1, -1};
     if (!empty) {
         mshost::LaunchEnv env{c->num_cus, st};
         auto *ctl = static_cast<mshost::CubeControl *>(d_workspace);
         uint64_t *V[3];
         for (int k = 0; k < 3; ++k) V[k] = mshost::cube_volume(d_workspace, D, M, N, k);
-        const uint64_t NONE = ~0ull;
-        // the first set voxel of the last x pass, read back through pinned memory
-        auto first_of = [&](uint64_t *f) -> ms_status {
-            if (hipMemcpyAsync(c->pinned, &ctl->first, sizeof(uint64_t), hipMemcpyDeviceToHost,
+        const int64_t smax = std::min(D, std::min(M, N));
+        // E_1: the input copied into volume 0 with its padding cleared; then the search runs on
+        // the device (gallop, then bisection, decided by a one-thread kernel after each probe),
+        // which writes d_out when done.  The host enqueues probes in rounds of PROBES_PER_ROUND
+        // and reads the phase once per round: a round that finds the search done costs only its
+        // idle launches, and no probe waits for the host.
+        constexpr int PROBES_PER_ROUND = 8;
+        int lg = 0;
+        while ((int64_t(1) << lg) < smax) ++lg;
+        const int rounds = (2 * lg + 2 + PROBES_PER_ROUND - 1) / PROBES_PER_ROUND + 1;
+        if (mshost::launch_cube_begin(env, ctl, smax) != hipSuccess ||
+            mshost::launch_cube_pass(env, 2, d_bits, ld_words, V[0], D, M, N, 0, ctl) !=
+                hipSuccess ||
+            mshost::launch_cube_control(env, ctl, d_out, M, N) != hipSuccess)
+            return MS_ERR_HIP;
+        for (int round = 0; round < rounds; ++round) {
+            for (int k = 0; k < PROBES_PER_ROUND; ++k)
+                if (mshost::launch_cube_probe(env, V, D, M, N, ctl) != hipSuccess ||
+                    mshost::launch_cube_control(env, ctl, d_out, M, N) != hipSuccess)
+                    return MS_ERR_HIP;
+            if (hipMemcpyAsync(c->pinned, &ctl->phase, sizeof(int32_t), hipMemcpyDeviceToHost,
                                st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return MS_ERR_HIP;
-            *f = c->pinned[0];
-            return MS_OK;
-        };
-        // E_1: the input copied into volume 0 with its padding cleared
-        if (mshost::launch_cube_pass(env, 2, d_bits, ld_words, V[0], D, M, N, 0, ctl) !=
-            hipSuccess)
-            return MS_ERR_HIP;
-        uint64_t fa = NONE;
-        if ((s = first_of(&fa)) != MS_OK) return s;
-        if (fa != NONE) {
-            int cur = 0;
-            int64_t a = 1;
-            const int64_t smax = std::min(D, std::min(M, N));
-            // E_{a+b} from E_a (b <= a) in one pass; returns its first set voxel
-            auto step = [&](int64_t b, int *out, uint64_t *f) -> ms_status {
-                const int x = (cur + 1) % 3;
-                if (mshost::launch_cube_step(env, V[cur], V[x], D, M, N, b, ctl) != hipSuccess)
-                    return MS_ERR_HIP;
-                *out = x;
-                return first_of(f);
-            };
-            // gallop: a = 1, 2, 4, ... while E_{2a} is non-empty
-            int64_t failed = 0;
-            while (a < smax) {
-                const int64_t b = std::min(a, smax - a);
-                int out = 0;
-                uint64_t f = NONE;
-                if ((s = step(b, &out, &f)) != MS_OK) return s;
-                if (f == NONE) {
-                    failed = b;
-                    break;
-                }
-                cur = out;
-                a += b;
-                fa = f;
-            }
-            // the side is in [a, a + failed - 1]: add powers of two, largest first
-            const int64_t limit = a + failed - 1;
-            int64_t bstep = 1;
-            while (bstep * 2 <= failed - 1) bstep *= 2;
-            for (; failed > 1 && bstep >= 1; bstep /= 2) {
-                if (a + bstep > limit) continue;
-                int out = 0;
-                uint64_t f = NONE;
-                if ((s = step(bstep, &out, &f)) != MS_OK) return s;
-                if (f != NONE) {
-                    cur = out;
-                    a += bstep;
-                    fa = f;
-                }
-            }
-            const int64_t plane = M * N;
-            res.side = a;
-            res.z = (int64_t)(fa / (uint64_t)plane);
-            const int64_t rem = (int64_t)(fa % (uint64_t)plane);
-            res.y = rem / N;
-            res.x = rem % N;
+            int32_t phase = 0;
+            std::memcpy(&phase, c->pinned, sizeof(phase));
+            if (phase == mshost::CUBE_DONE) return MS_OK;
         }
+        return MS_ERR_HIP;  // more probes than the bound on the search allows
     }
-    // the result through pinned memory (d_out may be device or pinned host memory)
+    // an empty volume: the result through pinned memory (d_out may be device or pinned host
+    // memory)
+    const ms_cube res{0, -1, -1, -1};
     std::memcpy(c->pinned, &res, sizeof(res));
     if (hipMemcpyAsync(d_out, c->pinned, sizeof(res), hipMemcpyDefault, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)

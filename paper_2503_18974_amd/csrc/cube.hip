@@ -6,10 +6,10 @@
 //     E_{a+b}(z, y, x) = AND over (dz, dy, dx) in {0, b}^3 of E_a(z - dz, y - dy, x - dx),
 // and that AND is separable: one pass per axis, each ANDing the volume with itself shifted by b.
 // E_{k+1} is a subset of E_k, so the side S is found by galloping (E_1, E_2, E_4, ... until one is
-// empty) and bisecting, as in the plane case.  A probe step takes the eight shifted copies in one
-// pass (k_cube_step; the separable single-axis pass k_cube_pass copies the input first), which
-// also reports whether the result is empty and its first set voxel in (z, y, x) order, which for
-// E_S is the reported corner.
+// empty) and bisecting, as in the plane case.  A probe takes the eight shifted copies in one pass
+// (k_cube_probe; the single-axis pass k_cube_pass copies the input first), which also reports
+// whether the result is empty and its first set voxel in (z, y, x) order, which for E_S is the
+// reported corner.  A one-thread kernel after each probe steers the search on the device.
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -73,15 +73,22 @@ __global__ __launch_bounds__(256) void k_cube_pass(const uint64_t *__restrict__ 
     }
 }
 
-// One probe step in one pass: dst = E_{a+d} from src = E_a, the AND of the eight copies of src
-// shifted by 0 or d along each axis, taken directly (four (z, y) corner rows, each with its
-// x-shifted self) rather than as three separable passes; the rows the shifts reach are mostly
-// still in the L2 from neighbouring threads.  Voxels shifted in from outside are zeros.  Also
-// lowers ctl->first to dst's first set voxel, as the x pass does.
-__global__ __launch_bounds__(256) void k_cube_step(const uint64_t *__restrict__ src,
-                                                   uint64_t *__restrict__ dst, uint32_t D,
-                                                   uint32_t M, int64_t n, uint32_t W, uint32_t d,
-                                                   mshost::CubeControl *ctl) {
+// One probe in one pass: E_{a+b} from E_a, the AND of the eight copies of E_a shifted by 0 or b
+// along each axis, taken directly (four (z, y) corner rows, each with its x-shifted self) rather
+// than as three single-axis passes; the rows the shifts reach are mostly still in the L2 from
+// neighbouring threads.  Voxels shifted in from outside are zeros.  The shift and the volumes
+// come from the search state; once the search is done the launch does nothing.  Also lowers
+// ctl->first to the result's first set voxel, as the x pass does.
+__global__ __launch_bounds__(256) void k_cube_probe(uint64_t *V0, uint64_t *V1, uint64_t *V2,
+                                                    uint32_t D, uint32_t M, int64_t n, uint32_t W,
+                                                    mshost::CubeControl *ctl) {
+    const int32_t phase = uniform(__hip_atomic_load(&ctl->phase, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT));
+    if (phase != mshost::CUBE_GALLOP && phase != mshost::CUBE_BISECT) return;
+    const int32_t cur = uniform(ctl->cur), nxt = uniform(ctl->nxt);
+    const uint32_t d = (uint32_t)uniform((int32_t)ctl->b);
+    const uint64_t *__restrict__ src = cur == 0 ? V0 : (cur == 1 ? V1 : V2);
+    uint64_t *__restrict__ dst = nxt == 0 ? V0 : (nxt == 1 ? V1 : V2);
     const uint32_t total = D * M * W;
     const uint64_t lastmask = last_word_mask(n);
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -124,6 +131,87 @@ __global__ __launch_bounds__(256) void k_cube_step(const uint64_t *__restrict__ 
     }
 }
 
+__global__ void k_cube_begin(mshost::CubeControl *ctl, int64_t smax) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    ctl->first = ~0ull;
+    ctl->fa = ~0ull;
+    ctl->a = ctl->b = ctl->failed = ctl->limit = ctl->bstep = 0;
+    ctl->smax = smax;
+    ctl->phase = mshost::CUBE_INIT;
+    ctl->cur = 0;
+    ctl->nxt = 1;
+}
+
+// After a pass: take its first set voxel, choose the next shift, clear the voxel word for the
+// next probe.  Gallop a = 1, 2, 4, ... (shift min(a, smax - a)) while E_{a+b} is non-empty; after
+// the first empty one (shift `failed`) the side is in [a, a + failed - 1], and powers of two
+// below `failed`, largest first, are added while the sum stays in range and E stays non-empty.
+// Done: S = a and the corner from E_a's first voxel go to *out.
+__global__ void k_cube_control(mshost::CubeControl *ctl, ms_cube *out, int64_t M, int64_t n) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    mshost::CubeControl &c = *ctl;
+    if (c.phase == mshost::CUBE_DONE) return;
+    const unsigned long long f = c.first;
+    const bool got = f != ~0ull;
+    bool done = false;
+    bool bisect_next = false;
+    if (c.phase == mshost::CUBE_INIT) {
+        if (!got) {
+            *out = ms_cube{0, -1, -1, -1};
+            c.phase = mshost::CUBE_DONE;
+            return;
+        }
+        c.fa = f;
+        c.a = 1;
+        c.cur = 0;
+        if (c.a < c.smax) {
+            c.b = c.a < c.smax - c.a ? c.a : c.smax - c.a;
+            c.phase = mshost::CUBE_GALLOP;
+        } else {
+            done = true;
+        }
+    } else if (c.phase == mshost::CUBE_GALLOP) {
+        if (got) {
+            c.cur = c.nxt;
+            c.a += c.b;
+            c.fa = f;
+            if (c.a < c.smax) c.b = c.a < c.smax - c.a ? c.a : c.smax - c.a;
+            else done = true;
+        } else {
+            c.failed = c.b;
+            c.limit = c.a + c.failed - 1;
+            int64_t bs = 1;
+            while (bs * 2 <= c.failed - 1) bs *= 2;
+            c.bstep = bs;
+            c.phase = mshost::CUBE_BISECT;
+            bisect_next = true;
+        }
+    } else {  // CUBE_BISECT: the probe just run added bstep
+        if (got) {
+            c.cur = c.nxt;
+            c.a += c.b;
+            c.fa = f;
+        }
+        c.bstep /= 2;
+        bisect_next = true;
+    }
+    if (bisect_next) {
+        while (c.bstep >= 1 && c.a + c.bstep > c.limit) c.bstep /= 2;
+        if (c.failed > 1 && c.bstep >= 1) c.b = c.bstep;
+        else done = true;
+    }
+    if (done) {
+        const unsigned long long plane = (unsigned long long)M * (unsigned long long)n;
+        const unsigned long long rem = c.fa % plane;
+        *out = ms_cube{c.a, (int64_t)(c.fa / plane), (int64_t)(rem / (unsigned long long)n),
+                       (int64_t)(rem % (unsigned long long)n)};
+        c.phase = mshost::CUBE_DONE;
+        return;
+    }
+    c.nxt = (c.cur + 1) % 3;
+    c.first = ~0ull;
+}
+
 __global__ void k_cube_reset(mshost::CubeControl *ctl) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->first = ~0ull;
 }
@@ -145,17 +233,25 @@ uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k) {
                                         (size_t)k * ((vol + 255) & ~(size_t)255));
 }
 
-hipError_t launch_cube_step(const LaunchEnv &env, const uint64_t *src, uint64_t *dst, int64_t D,
-                            int64_t M, int64_t n, int64_t d, CubeControl *ctl) {
+hipError_t launch_cube_begin(const LaunchEnv &env, CubeControl *ctl, int64_t smax) {
+    hipLaunchKernelGGL(msk::k_cube_begin, dim3(1), dim3(64), 0, env.stream, ctl, smax);
+    return hipGetLastError();
+}
+
+hipError_t launch_cube_control(const LaunchEnv &env, CubeControl *ctl, ms_cube *out, int64_t M,
+                               int64_t n) {
+    hipLaunchKernelGGL(msk::k_cube_control, dim3(1), dim3(64), 0, env.stream, ctl, out, M, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cube_probe(const LaunchEnv &env, uint64_t *const V[3], int64_t D, int64_t M,
+                             int64_t n, CubeControl *ctl) {
     const int64_t W = std::max<int64_t>(1, (n + 63) / 64);
     const int64_t total = D * M * W;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256,
                                                                    (int64_t)env.num_cus * 16));
-    hipLaunchKernelGGL(msk::k_cube_reset, dim3(1), dim3(64), 0, env.stream, ctl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(msk::k_cube_step, dim3((unsigned)blocks), dim3(256), 0, env.stream, src,
-                       dst, (uint32_t)D, (uint32_t)M, n, (uint32_t)W, (uint32_t)d, ctl);
+    hipLaunchKernelGGL(msk::k_cube_probe, dim3((unsigned)blocks), dim3(256), 0, env.stream, V[0],
+                       V[1], V[2], (uint32_t)D, (uint32_t)M, n, (uint32_t)W, ctl);
     return hipGetLastError();
 }
 

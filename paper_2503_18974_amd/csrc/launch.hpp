@@ -153,10 +153,18 @@ hipError_t launch_max_rect(const LaunchEnv &env, const uint64_t *bits, int64_t m
 
 // Largest all-ones cube (cube.hip).  The workspace holds a 256-byte control block and three
 // volumes of D x M x ceil(n / 64) words; cube_volume(ws, .., k) is volume k (k < 3).
+// The search state lives on the device: a one-thread control kernel after each probe reads the
+// probe's first set voxel and decides the next shift (gallop, then bisection), so the host only
+// reads the phase once per round of probes.
+enum { CUBE_INIT = 0, CUBE_GALLOP = 1, CUBE_BISECT = 2, CUBE_DONE = 3 };
 struct CubeControl {
     unsigned long long first;  // smallest z * M * n + y * n + x of a set voxel (~0: empty)
-    uint64_t pad[7];
+    unsigned long long fa;     // the same for E_a, the largest non-empty E so far
+    int64_t a, b;              // E_a is in volume cur; the probe in flight builds E_{a+b} in nxt
+    int64_t failed, limit, bstep, smax;  // bisection: the side is in [a, limit]
+    int32_t phase, cur, nxt, pad;
 };
+static_assert(sizeof(CubeControl) <= 256, "cube control block");
 size_t cube_workspace_bytes(int64_t D, int64_t M, int64_t n);
 uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k);
 // dst = src AND src shifted by d along `axis` (0 = z, 1 = y, 2 = x); the x pass also resets and
@@ -164,9 +172,13 @@ uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k);
 hipError_t launch_cube_pass(const LaunchEnv &env, int axis, const uint64_t *src, int64_t lds,
                             uint64_t *dst, int64_t D, int64_t M, int64_t n, int64_t d,
                             CubeControl *ctl);
-// dst = E_{a+d} from src = E_a (both with row stride ceil(n / 64)) in one pass, resetting and then
-// setting ctl->first for dst.
-hipError_t launch_cube_step(const LaunchEnv &env, const uint64_t *src, uint64_t *dst, int64_t D,
-                            int64_t M, int64_t n, int64_t d, CubeControl *ctl);
+// The search on the device: cube_begin sets the state up (before the copy pass of the input
+// into volume 0), cube_control advances it after a pass and writes *out once it is done, and
+// cube_probe runs the next probe (E_{a+b} from E_a, volumes from the state) unless it is done.
+hipError_t launch_cube_begin(const LaunchEnv &env, CubeControl *ctl, int64_t smax);
+hipError_t launch_cube_control(const LaunchEnv &env, CubeControl *ctl, ms_cube *out, int64_t M,
+                               int64_t n);
+hipError_t launch_cube_probe(const LaunchEnv &env, uint64_t *const V[3], int64_t D, int64_t M,
+                             int64_t n, CubeControl *ctl);
 
 } // namespace mshost
