@@ -676,8 +676,7 @@ ms_status ms_max_cube(ms_ctx *ctx, const uint64_t *d_bits, int64_t D, int64_t M,
         while ((int64_t(1) << lg) < smax) ++lg;
         const int rounds = (2 * lg + 2 + PROBES_PER_ROUND - 1) / PROBES_PER_ROUND + 1;
         if (mshost::launch_cube_begin(env, ctl, smax) != hipSuccess ||
-            mshost::launch_cube_pass(env, 2, d_bits, ld_words, V[0], D, M, N, 0, ctl) !=
-                hipSuccess ||
+            mshost::launch_cube_copy(env, d_bits, ld_words, V[0], D, M, N, ctl) != hipSuccess ||
             mshost::launch_cube_control(env, ctl, d_out, M, N) != hipSuccess)
             return MS_ERR_HIP;
         for (int round = 0; round < rounds; ++round) {

@@ -1,30 +1,26 @@
 // cube.hip -- largest all-ones cube of a packed binary volume (the higher-dimensional
-// generalization the paper proposes as future work, Section 6), and its host-side search.
+// generalization the paper proposes as future work, Section 6), and the search over its side.
 //
 // E_k marks the voxels that are the far corner (largest z, y and x) of an all-ones k x k x k cube.
 // Since cubes of side a tile a cube of side a + b (b <= a) when shifted by 0 or b along each axis,
-//     E_{a+b}(z, y, x) = AND over (dz, dy, dx) in {0, b}^3 of E_a(z - dz, y - dy, x - dx),
-// and that AND is separable: one pass per axis, each ANDing the volume with itself shifted by b.
+//     E_{a+b}(z, y, x) = AND over (dz, dy, dx) in {0, b}^3 of E_a(z - dz, y - dy, x - dx).
 // E_{k+1} is a subset of E_k, so the side S is found by galloping (E_1, E_2, E_4, ... until one is
 // empty) and bisecting, as in the plane case.  A probe takes the eight shifted copies in one pass
-// (k_cube_probe; the single-axis pass k_cube_pass copies the input first), which also reports
-// whether the result is empty and its first set voxel in (z, y, x) order, which for E_S is the
-// reported corner.  A one-thread kernel after each probe steers the search on the device.
+// (k_cube_probe, after k_cube_copy has copied the input into E_1), which also reports whether the
+// result is empty and its first set voxel in (z, y, x) order, which for E_S is the reported
+// corner.  A one-thread kernel after each probe steers the search on the device.
 #include "device.hpp"
 #include "launch.hpp"
 
 namespace msk {
 
-// dst = src AND src shifted by d along AXIS (0 = z, 1 = y, 2 = x); voxels shifted in from outside
-// the volume are zeros.  Volumes are D planes of M rows of W words (row stride W, plane stride
-// M * W), padding bits past n zero.  The x pass (FIRST) also lowers ctl->first to the smallest
-// position z * M * n + y * n + x of a set voxel of dst.  With d = 0 the pass copies src (read
-// with row stride lds and plane stride M * lds) and clears its padding bits.
-template <int AXIS, bool FIRST>
-__global__ __launch_bounds__(256) void k_cube_pass(const uint64_t *__restrict__ src, int64_t lds,
+// E_1: the input volume (row stride lds words, plane stride M * lds) copied into a compact volume
+// (row stride W) with its padding bits cleared, lowering ctl->first to the smallest position
+// z * M * n + y * n + x of a set voxel.
+__global__ __launch_bounds__(256) void k_cube_copy(const uint64_t *__restrict__ src, int64_t lds,
                                                    uint64_t *__restrict__ dst, uint32_t D,
                                                    uint32_t M, int64_t n, uint32_t W,
-                                                   uint32_t d, mshost::CubeControl *ctl) {
+                                                   mshost::CubeControl *ctl) {
     const uint32_t total = D * M * W;
     const uint64_t lastmask = last_word_mask(n);
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -32,44 +28,30 @@ __global__ __launch_bounds__(256) void k_cube_pass(const uint64_t *__restrict__ 
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
         const uint32_t row = t / W, w = t - row * W;
         const uint32_t z = row / M, y = row - z * M;
-        const uint64_t *s = src + ((int64_t)z * M + y) * lds;
-        uint64_t v = s[w], o;
-        if (AXIS == 0) {
-            o = z >= d ? s[-(int64_t)d * M * lds + w] : 0ull;
-        } else if (AXIS == 1) {
-            o = y >= d ? s[-(int64_t)d * lds + w] : 0ull;
-        } else {
-            const uint32_t q = d >> 6, r = d & 63;
-            const uint64_t hi = w >= q ? s[w - q] : 0ull;
-            const uint64_t lo = w >= q + 1 ? s[w - q - 1] : 0ull;
-            o = r ? ((hi << r) | (lo >> (64 - r))) : hi;
-        }
-        v &= o;
+        uint64_t v = src[((int64_t)z * M + y) * lds + w];
         if (w == W - 1) v &= lastmask;
         dst[(int64_t)row * W + w] = v;
-        if (FIRST && v) {
+        if (v) {
             const unsigned long long p =
                 ((unsigned long long)z * M + y) * (unsigned long long)n +
                 (unsigned long long)w * 64 + (unsigned long long)__builtin_ctzll(v);
             best = p < best ? p : best;
         }
     }
-    if (FIRST) {
-        // one atomic per block, and only when it can lower the current first position
-        __shared__ unsigned long long s_min[4];
-        unsigned long long wb = best;
+    // one atomic per block, and only when it can lower the current first position
+    __shared__ unsigned long long s_min[4];
+    unsigned long long wb = best;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long o2 = __shfl_xor(wb, off);
-            wb = o2 < wb ? o2 : wb;
-        }
-        if (__lane_id() == 0) s_min[threadIdx.x / WAVE] = wb;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long b = s_min[0];
-            for (int k = 1; k < 4; ++k) b = s_min[k] < b ? s_min[k] : b;
-            if (b != ~0ull && b < load_relaxed(&ctl->first)) atomicMin(&ctl->first, b);
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o2 = __shfl_xor(wb, off);
+        wb = o2 < wb ? o2 : wb;
+    }
+    if (__lane_id() == 0) s_min[threadIdx.x / WAVE] = wb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = s_min[0];
+        for (int k = 1; k < 4; ++k) b = s_min[k] < b ? s_min[k] : b;
+        if (b != ~0ull && b < load_relaxed(&ctl->first)) atomicMin(&ctl->first, b);
     }
 }
 
@@ -212,10 +194,6 @@ __global__ void k_cube_control(mshost::CubeControl *ctl, ms_cube *out, int64_t M
     c.first = ~0ull;
 }
 
-__global__ void k_cube_reset(mshost::CubeControl *ctl) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->first = ~0ull;
-}
-
 } // namespace msk
 
 namespace mshost {
@@ -255,28 +233,14 @@ hipError_t launch_cube_probe(const LaunchEnv &env, uint64_t *const V[3], int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_cube_pass(const LaunchEnv &env, int axis, const uint64_t *src, int64_t lds,
-                            uint64_t *dst, int64_t D, int64_t M, int64_t n, int64_t d,
-                            CubeControl *ctl) {
+hipError_t launch_cube_copy(const LaunchEnv &env, const uint64_t *src, int64_t lds,
+                            uint64_t *dst, int64_t D, int64_t M, int64_t n, CubeControl *ctl) {
     const int64_t W = std::max<int64_t>(1, (n + 63) / 64);
     const int64_t total = D * M * W;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256,
                                                                    (int64_t)env.num_cus * 16));
-    const dim3 g((unsigned)blocks), b(256);
-    const uint32_t D32 = (uint32_t)D, M32 = (uint32_t)M, W32 = (uint32_t)W, d32 = (uint32_t)d;
-    if (axis == 2) {
-        hipLaunchKernelGGL(msk::k_cube_reset, dim3(1), dim3(64), 0, env.stream, ctl);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((msk::k_cube_pass<2, true>), g, b, 0, env.stream, src, lds, dst, D32,
-                           M32, n, W32, d32, ctl);
-    } else if (axis == 0) {
-        hipLaunchKernelGGL((msk::k_cube_pass<0, false>), g, b, 0, env.stream, src, lds, dst, D32,
-                           M32, n, W32, d32, ctl);
-    } else {
-        hipLaunchKernelGGL((msk::k_cube_pass<1, false>), g, b, 0, env.stream, src, lds, dst, D32,
-                           M32, n, W32, d32, ctl);
-    }
+    hipLaunchKernelGGL(msk::k_cube_copy, dim3((unsigned)blocks), dim3(256), 0, env.stream, src,
+                       lds, dst, (uint32_t)D, (uint32_t)M, n, (uint32_t)W, ctl);
     return hipGetLastError();
 }
 

@@ -167,11 +167,10 @@ struct CubeControl {
 static_assert(sizeof(CubeControl) <= 256, "cube control block");
 size_t cube_workspace_bytes(int64_t D, int64_t M, int64_t n);
 uint64_t *cube_volume(void *ws, int64_t D, int64_t M, int64_t n, int k);
-// dst = src AND src shifted by d along `axis` (0 = z, 1 = y, 2 = x); the x pass also resets and
-// then sets ctl->first for dst.  src has row stride lds words; dst has ceil(n / 64).
-hipError_t launch_cube_pass(const LaunchEnv &env, int axis, const uint64_t *src, int64_t lds,
-                            uint64_t *dst, int64_t D, int64_t M, int64_t n, int64_t d,
-                            CubeControl *ctl);
+// E_1: the input (row stride lds words) copied into dst (row stride ceil(n / 64)) with its padding
+// cleared; lowers ctl->first to its first set voxel (cube_begin cleared it).
+hipError_t launch_cube_copy(const LaunchEnv &env, const uint64_t *src, int64_t lds,
+                            uint64_t *dst, int64_t D, int64_t M, int64_t n, CubeControl *ctl);
 // The search on the device: cube_begin sets the state up (before the copy pass of the input
 // into volume 0), cube_control advances it after a pass and writes *out once it is done, and
 // cube_probe runs the next probe (E_{a+b} from E_a, volumes from the state) unless it is done.
