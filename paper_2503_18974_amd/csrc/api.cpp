@@ -71,6 +71,7 @@ struct ms_ctx {
     void *scratch = nullptr;
     int64_t state_words = 0;
     int64_t sat_bytes = 0;
+    int64_t strip_words = 0;  // boundary words of the strip sweep (zeroed with the header)
     bool dirty = false;
     bool has_forced = false;
     ms_config forced{};
@@ -212,14 +213,20 @@ bool config_valid(const ms_config &cfg) {
 
 // Make sure the context scratch holds the serial-pass state and the probe's saturation bytes
 // for an m x n matrix.
+uint64_t *strips_of(ms_ctx *c);
+
 ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     const int64_t nwords = std::max<int64_t>(1, cdiv(n, 64));
     const int64_t tiles = mshost::max_probe_tiles(m, n);
+    const int64_t strips = mshost::strip_words_needed(m, n);
     const mshost::LaunchEnv env{c->num_cus, stream};
-    if (c->scratch && c->state_words >= nwords && c->sat_bytes >= tiles) {
+    if (c->scratch && c->state_words >= nwords && c->sat_bytes >= tiles &&
+        c->strip_words >= strips) {
         if (c->dirty) {
+            // the header's epoch tags the strip words: both start again from zero
             if (mshost::launch_zero_header(env, c->scratch, sizeof(mshost::ScratchHeader)) !=
-                hipSuccess)
+                    hipSuccess ||
+                mshost::launch_zero_u64(env, strips_of(c), c->strip_words) != hipSuccess)
                 return MS_ERR_HIP;
             c->dirty = false;
         }
@@ -227,12 +234,16 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     }
     const int64_t words = std::max<int64_t>(nwords, c->state_words);
     const int64_t sat = std::max<int64_t>(tiles, c->sat_bytes);
-    // header | serial state | saturation bytes | per-tile bounds (int32) | probe box records
+    const int64_t swords = std::max<int64_t>(strips, c->strip_words);
+    // header | serial state | saturation bytes | per-tile bounds (int32) | probe box records |
+    // strip words
     const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t) +
                          (((size_t)sat + 255) & ~(size_t)255) +
                          (((size_t)sat * sizeof(int32_t) + 255) & ~(size_t)255) +
-                         (size_t)mshost::max_probe_blocks(c->num_cus) *
-                             mshost::BOX_RECORD_WORDS * sizeof(uint32_t);
+                         (((size_t)mshost::max_probe_blocks(c->num_cus) *
+                               mshost::BOX_RECORD_WORDS * sizeof(uint32_t) + 255) &
+                          ~(size_t)255) +
+                         (size_t)swords * sizeof(uint64_t);
     if (c->scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
@@ -245,13 +256,17 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     // the header is zeroed on the caller's stream, ahead of the search launched there next (a
     // memset on the null stream may still be pending when a non-blocking stream runs the probe,
     // and would then erase keys it pushed)
-    if (mshost::launch_zero_header(env, p, sizeof(mshost::ScratchHeader)) != hipSuccess) {
-        (void)hipFree(p);
-        return MS_ERR_HIP;
-    }
     c->scratch = p;
     c->state_words = words;
     c->sat_bytes = sat;
+    c->strip_words = swords;
+    if (mshost::launch_zero_header(env, p, sizeof(mshost::ScratchHeader)) != hipSuccess ||
+        mshost::launch_zero_u64(env, strips_of(c), swords) != hipSuccess) {
+        c->scratch = nullptr;
+        c->state_words = c->sat_bytes = c->strip_words = 0;
+        (void)hipFree(p);
+        return MS_ERR_HIP;
+    }
     c->dirty = false;
     return MS_OK;
 }
@@ -268,6 +283,20 @@ uint32_t *box_records_of(ms_ctx *c) {
     return reinterpret_cast<uint32_t *>(
         reinterpret_cast<char *>(bounds_of(c)) +
         (((size_t)c->sat_bytes * sizeof(int32_t) + 255) & ~(size_t)255));
+}
+uint64_t *strips_of(ms_ctx *c) {
+    if (c->strip_words == 0) return nullptr;
+    return reinterpret_cast<uint64_t *>(
+        reinterpret_cast<char *>(box_records_of(c)) +
+        (((size_t)mshost::max_probe_blocks(c->num_cus) * mshost::BOX_RECORD_WORDS *
+              sizeof(uint32_t) + 255) & ~(size_t)255));
+}
+// The strip words for an m x n call, or nullptr (the kernels then keep the one-wave sweep)
+// when the scratch holds too few of them for that shape.
+uint64_t *strips_for(ms_ctx *c, int64_t m, int64_t n) {
+    const int64_t need = cdiv(cdiv(std::max<int64_t>(n, 1), 64), (int64_t)mshost::STRIP_WORDS) *
+                         std::max<int64_t>(m, 1) * 2;
+    return c->strip_words >= need ? strips_of(c) : nullptr;
 }
 int32_t *state_of(ms_ctx *c) {
     return reinterpret_cast<int32_t *>(static_cast<char *>(c->scratch) +
@@ -299,7 +328,7 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
     } else {
         e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
                                       state_of(c), sat_of(c), bounds_of(c), box_records_of(c),
-                                      out);
+                                      out, strips_for(c, m, n));
     }
     if (e != hipSuccess) {
         c->dirty = true;
@@ -441,7 +470,7 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
                                      hdr_of(c)->big_box};
     hipError_t e = mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m, n,
                                              ld_words, d_dp, ld_dp, &hdr_of(c)->result,
-                                             state_of(c), &regions);
+                                             state_of(c), &regions, hdr_of(c), strips_for(c, m, n));
     return hip_status(e);
 }
 
@@ -476,7 +505,8 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
                                      hdr_of(c)->big_box};
     return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m,
                                                 n, ld_words, d_dp, ld_dp, d_max, state_of(c),
-                                                same ? &regions : nullptr));
+                                                same ? &regions : nullptr, hdr_of(c),
+                                                strips_for(c, m, n)));
 }
 
 ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_t count,
@@ -839,7 +869,9 @@ ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                 return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows,
                                                             d_bits, m, n, ld_words, d_dp_scratch,
                                                             ld_dp, &hdr_of(c)->result,
-                                                            state_of(c)));
+                                                            state_of(c), nullptr,
+                                                            hdr_of(c),
+                                                            strips_for(c, m, n)));
             }, &t);
             if (s == MS_OK && t < best_map) {
                 best_map = t;

@@ -151,12 +151,203 @@ __device__ void write_result(unsigned long long key, int64_t n, ms_square *dst) 
     *dst = r;
 }
 
-// One wave: key -> result (serial pass if a square was too wide for the resolve pass), then
-// clear the header for the next call.
+// ----------------------------------------------------------------------------------------------
+// Strip sweep: the recurrence over the whole matrix, for a square too wide for the windowed
+// passes, by every wave that takes part.  The columns are cut into strips of STRIP_WORDS words;
+// a wave takes strips in ticket order and walks its strip top to bottom with the column heights
+// and previous-row dp of its columns in registers.  Strip s needs, per row, the row run and the
+// dp at the last column of strip s - 1, which that strip publishes 64 rows at a time as 64-bit
+// words tagged with the launch's epoch, so the reader polls the words themselves (no flag, no
+// fence).  A strip only waits on the strip before it, whose ticket was taken earlier by a wave
+// that is running, so every wait ends; one that still outlasts SPIN_LIMIT polls gives up and
+// sets hdr->timeout to the launch's tag, after which no wait of that launch lingers.  The row
+// run is published capped at RUN_CAP: min(m, n) < 2^20, so when n > RUN_CAP every column height
+// is below the cap and the cap never decides a minimum.
+// ----------------------------------------------------------------------------------------------
+constexpr int32_t RUN_CAP = (1 << 20) - 1;
+constexpr int32_t HEIGHT_CAP = 1 << 30;
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
+
+__device__ __forceinline__ void store_relaxed_u64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)v, l);
+}
+
+// The next strip for the calling wave: one atomic add on a counter holding epoch << 32 | count.
+// The first takers of a launch find an earlier launch's epoch there; one of them installs this
+// launch's epoch with ticket 0 taken (a compare-and-swap that only they race on), and the others
+// add again.  The counter thus never needs a reset.
+__device__ int64_t take_strip(unsigned long long *tick, uint32_t epoch) {
+    uint32_t t = 0;
+    if (__lane_id() == 0) {
+        for (bool got = false; !got;) {
+            const unsigned long long old = atomicAdd(tick, 1ull);
+            if ((uint32_t)(old >> 32) == epoch) {
+                t = (uint32_t)old;
+                break;
+            }
+            const unsigned long long mine = ((unsigned long long)epoch << 32) | 1ull;
+            unsigned long long cur = old + 1ull;
+            for (;;) {
+                const unsigned long long seen = atomicCAS(tick, cur, mine);
+                if (seen == cur) {
+                    t = 0;
+                    got = true;
+                    break;
+                }
+                if ((uint32_t)(seen >> 32) == epoch) break;  // installed by another wave
+                cur = seen;
+            }
+        }
+    }
+    return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(t);
+}
+
+// Waves that take part in a sweep of nstrips strips: one per strip at most, so that the ticket
+// counter sees few contenders (a wave finishing its strip takes the next one).
+__device__ __forceinline__ int64_t strip_takers(int64_t nstrips, int64_t nwave) {
+    return nstrips < nwave ? nstrips : nwave;
+}
+
+__device__ __forceinline__ int64_t strip_count(int64_t n) {
+    return (((n + 63) >> 6) + mshost::STRIP_WORDS - 1) / mshost::STRIP_WORDS;
+}
+
+template <bool STORE>
+__device__ void strip_sweep(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                            int32_t *__restrict__ dp, int64_t ld_dp, int64_t s,
+                            unsigned long long *bnd, uint32_t epoch, uint32_t *timeout,
+                            Track &tr) {
+    constexpr int SW = mshost::STRIP_WORDS;
+    const int lane = __lane_id();
+    const int64_t nwords = (n + 63) >> 6;
+    const uint64_t lastmask = last_word_mask(n);
+    const unsigned long long tag = (unsigned long long)epoch + 1ull;
+    const int64_t w0 = s * SW;
+    unsigned long long *mine = bnd + s * m * 2;
+    const unsigned long long *left = s > 0 ? bnd + (s - 1) * m * 2 : nullptr;
+    const bool publish = s + 1 < strip_count(n);
+    int32_t H[SW], D[SW];
+#pragma unroll
+    for (int u = 0; u < SW; ++u) H[u] = D[u] = 0;
+    int32_t dl = 0;  // dp of the previous row at the column just left of the strip
+    // the strip's words of rows i0 .. i0 + 63, row i0 + l in lane l
+    auto load_rows = [&](int64_t i0, uint64_t(&v)[SW]) {
+        const int64_t i = i0 + lane;
+#pragma unroll
+        for (int u = 0; u < SW; ++u)
+            v[u] = i < m ? row_word(bits + i * ldw, w0 + u, nwords, lastmask) : 0ull;
+    };
+    uint64_t x[SW];
+    load_rows(0, x);
+    for (int64_t i0 = 0; i0 < m; i0 += WAVE) {
+        uint64_t nx[SW];
+        load_rows(i0 + WAVE, nx);
+        int32_t win = 0, din = 0;
+        if (left) {
+            const int64_t i = i0 + lane;
+            unsigned long long a = tag << 20, b = tag << 20;
+            if (i < m) {
+                a = load_relaxed(left + 2 * i);
+                b = load_relaxed(left + 2 * i + 1);
+            }
+            for (uint32_t polls = 0;; ++polls) {
+                const bool ok = (a >> 20) == tag && (b >> 20) == tag;
+                if (__ballot(!ok) == 0ull) break;
+                // once any wait of the launch has given up, none waits any longer
+                if (polls >= SPIN_LIMIT ||
+                    (polls % 1024u == 1023u && load_relaxed_u32(timeout) == epoch + 1u)) {
+                    if (lane == 0) atomicExch(timeout, epoch + 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+                if (!ok) {
+                    a = load_relaxed(left + 2 * i);
+                    b = load_relaxed(left + 2 * i + 1);
+                }
+            }
+            win = (int32_t)(a & 0xFFFFFull);
+            din = (int32_t)(b & 0xFFFFFull);
+        }
+        const int rows = (int)(m - i0 < WAVE ? m - i0 : WAVE);
+        int32_t ow = 0, od = 0;
+        for (int r = 0; r < rows; ++r) {
+            int32_t wc = __builtin_amdgcn_readlane(win, r);  // row run entering the strip
+            int32_t dleft = dl;                              // previous row, column left of word
+            dl = __builtin_amdgcn_readlane(din, r);
+            const int64_t i = i0 + r;
+#pragma unroll
+            for (int u = 0; u < SW; ++u) {
+                const uint64_t xv = lane_u64(x[u], r);
+                const int32_t a = (int32_t)((xv >> lane) & 1u);
+                const int32_t lo = (int32_t)__clzll(~(xv << (63 - lane)));
+                const int32_t wl = a ? ((lo == lane + 1) ? lane + 1 + wc : lo) : 0;
+                const int32_t h = a ? (H[u] < HEIGHT_CAP ? H[u] + 1 : HEIGHT_CAP) : 0;
+                const int32_t dprev = from_left_lane(D[u], dleft);
+                dleft = __builtin_amdgcn_readlane(D[u], WAVE - 1);
+                int32_t d = h < wl ? h : wl;
+                d = d < dprev + 1 ? d : dprev + 1;
+                if (!a) d = 0;
+                H[u] = h;
+                D[u] = d;
+                const int64_t c = (w0 + u) * 64 + lane;
+                if (c < n) {
+                    if (STORE) dp[i * ld_dp + c] = d;
+                    if (d > tr.v) {
+                        tr.v = d;
+                        tr.pos = i * n + c;
+                    }
+                }
+                wc = (xv == ~0ull) ? (wc < RUN_CAP - 64 ? wc + 64 : RUN_CAP) : leading_ones(xv);
+            }
+            const int32_t dlast = __builtin_amdgcn_readlane(D[SW - 1], WAVE - 1);
+            ow = lane == r ? wc : ow;
+            od = lane == r ? dlast : od;
+        }
+        if (publish && i0 + lane < m) {
+            const int64_t i = i0 + lane;
+            store_relaxed_u64(mine + 2 * i, (tag << 20) | (unsigned long long)(uint32_t)ow);
+            store_relaxed_u64(mine + 2 * i + 1, (tag << 20) | (unsigned long long)(uint32_t)od);
+        }
+#pragma unroll
+        for (int u = 0; u < SW; ++u) x[u] = nx[u];
+    }
+}
+
+// The map's sweep: the first strip_takers waves of the launch take strips until none is left;
+// the wave taking the launch's last ticket (each taker ends on one past the strips) bumps the
+// epoch for the next launch (every taker read it before its first ticket).
+__device__ void strip_map(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+                          int32_t *__restrict__ dp, int64_t ld_dp, mshost::ScratchHeader *hdr,
+                          unsigned long long *bnd) {
+    const int64_t nstrips = strip_count(n);
+    const int64_t takers = strip_takers(nstrips, ((int64_t)gridDim.x * blockDim.x) / WAVE);
+    if (wave_index() >= takers) return;
+    const uint32_t epoch = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->epoch));
+    for (;;) {
+        const int64_t s = take_strip(&hdr->tick, epoch);
+        if (s >= nstrips) {
+            if (s == nstrips + takers - 1 && __lane_id() == 0)
+                __hip_atomic_store(&hdr->epoch, epoch + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        Track tr{0, INT64_MAX};
+        strip_sweep<true>(bits, m, n, ldw, dp, ld_dp, s, bnd, epoch, &hdr->timeout, tr);
+    }
+}
+
+// One wave: key -> result (for a square too wide for the resolve pass, the strip sweep's key,
+// or without boundary words the one-wave serial pass), then clear the header for the next call
+// and bump its epoch.
 __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int64_t n,
                               int64_t ldw, mshost::ScratchHeader *hdr, int32_t *serial_state,
                               ms_square *out, const uint32_t *__restrict__ box_rec,
-                              int64_t nrec) {
+                              int64_t nrec, bool strips, uint32_t epoch) {
     const int lane = __lane_id();
     if (box_rec) {
         // fold the probe blocks' box records for the map of the same call
@@ -189,7 +380,11 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
     // both loads in flight together (device-scope: written by other waves' atomics)
     unsigned long long key = load_relaxed(&hdr->key);
     const uint32_t flag = load_relaxed_u32(&hdr->serial_flag);
-    if (flag) {
+    bool failed = false;
+    if (flag && strips) {
+        key = load_relaxed(&hdr->skey);
+        failed = load_relaxed_u32(&hdr->timeout) == epoch + 1u;
+    } else if (flag) {
         const int64_t nw64 = ((n + 63) >> 6) * 64;
         Track tr{0, INT64_MAX};
         serial_dp<false>(bits, m, n, ldw, nullptr, 0, serial_state, serial_state + nw64, tr);
@@ -198,12 +393,28 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
     }
     if (lane == 0) {
         write_result(key, n, &hdr->result);
-        if (out) write_result(key, n, out);
+        if (failed) hdr->result = ms_square{-1, -1, -1};
+        if (out) *out = hdr->result;
         hdr->key = 0;
         hdr->serial_flag = 0;
         hdr->nsat = 0;
         hdr->done = 0;
+        hdr->skey = 0;
+        hdr->fin = 0;
+        hdr->sdone = 0;
+        hdr->epoch = epoch + 1u;
     }
+}
+
+// One of the two arrivals that end a search with a strip sweep (the last resolve wave, and the
+// wave that finished the last strip): true for the second, which then writes the result.
+__device__ bool fin_arrive(mshost::ScratchHeader *hdr) {
+    __threadfence();
+    uint32_t f = 0;
+    if (__lane_id() == 0) f = atomicAdd(&hdr->fin, 1u);
+    f = (uint32_t)__builtin_amdgcn_readfirstlane(f);
+    if (f == 1u) __threadfence();
+    return f == 1u;
 }
 
 // After the probe: if any tile saturated, finish those tiles exactly, then the last wave to
@@ -226,15 +437,19 @@ __global__ __launch_bounds__(64 * RESOLVE_WAVES) void k_resolve(
     const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw, int64_t ntiles,
     int64_t ntx, mshost::ScratchHeader *hdr, const uint8_t *__restrict__ sat,
     int32_t *__restrict__ bounds, const uint32_t *__restrict__ box_rec, int64_t nrec,
-    int32_t *serial_state, ms_square *out) {
+    int32_t *serial_state, ms_square *out, unsigned long long *bnd) {
     __shared__ ResolveLds L;
     const int lane = __lane_id();
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int64_t nblk = gridDim.x;
     const uint32_t nsat = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->nsat));
+    // read before this wave's completion count, so before the result's wave bumps it
+    const uint32_t epoch = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->epoch));
+    const bool strips = bnd != nullptr;
     if (nsat == 0) {
-        if (wave == 0) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec);
+        if (wave == 0)
+            finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, strips, epoch);
         return;
     }
     if ((int64_t)nsat <= nblk) {
@@ -282,10 +497,36 @@ __global__ __launch_bounds__(64 * RESOLVE_WAVES) void k_resolve(
     uint32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&hdr->done, 1u);
     prev = (uint32_t)__shfl((int32_t)prev, 0);
-    if (prev == (uint32_t)(nwave - 1)) {
-        __threadfence();
-        finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec);
+    const bool last = prev == (uint32_t)(nwave - 1);
+    if (last) __threadfence();
+    // Every wave that raised the flag did so before its completion count, so the last wave sees
+    // it; an earlier wave that misses it only leaves the sweep to the others.
+    const bool sweep = strips && uniform((int32_t)load_relaxed_u32(&hdr->serial_flag)) != 0;
+    const int64_t nstrips = strip_count(n);
+    // the sweepers: the last strip_takers waves to arrive (the last one among them), which are
+    // the likeliest to have seen the flag
+    if (!sweep || nwave - 1 - (int64_t)prev >= strip_takers(nstrips, nwave)) {
+        if (last) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, strips,
+                                epoch);
+        return;
     }
+    // A square too wide for the resolve pass: the result waits for both the last wave's arrival
+    // and the last strip.
+    bool finish = last && fin_arrive(hdr);
+    for (;;) {
+        const int64_t st = take_strip(&hdr->tick, epoch);
+        if (st >= nstrips) break;
+        Track tr{0, INT64_MAX};
+        strip_sweep<false>(bits, m, n, ldw, nullptr, 0, st, bnd, epoch, &hdr->timeout, tr);
+        const Track w = wave_track(tr);
+        if (lane == 0 && w.v > 0) atomicMax(&hdr->skey, make_key(w.v, w.pos));
+        __threadfence();
+        uint32_t k = 0;
+        if (lane == 0) k = atomicAdd(&hdr->sdone, 1u);
+        k = (uint32_t)__builtin_amdgcn_readfirstlane(k);
+        if (k == (uint32_t)(nstrips - 1) && fin_arrive(hdr)) finish = true;
+    }
+    if (finish) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, strips, epoch);
 }
 
 // The narrow pass of the map (one wave per item, windows of NGMAX groups of 64 * CPL columns):
@@ -373,11 +614,16 @@ __device__ int64_t wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64
                           int32_t *__restrict__ dp, int64_t ld_dp, int64_t S, int64_t band_rows,
                           int32_t *serial_state, int vec_ok, bool region,
                           const int32_t *__restrict__ bounds, int64_t tile_rows,
-                          int64_t tile_ntx, BlockLds L, const uint32_t *box) {
+                          int64_t tile_ntx, BlockLds L, const uint32_t *box,
+                          mshost::ScratchHeader *hdr, unsigned long long *bnd) {
     constexpr int64_t GW = 256, NGB = 8, WIN = NGB * GW, REACH = WIN - 64;
     constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
     const int64_t hc = (S + 63) & ~(int64_t)63;
     if (hc > REACH) {
+        if (bnd) {  // every wave of the launch sweeps strips; every cell is stored
+            strip_map(bits, m, n, ldw, dp, ld_dp, hdr, bnd);
+            return -1;
+        }
         if (blockIdx.x == 0 && threadIdx.x < WAVE) {
             const int64_t nw64 = ((n + 63) >> 6) * 64;
             Track tr{0, INT64_MAX};
@@ -513,7 +759,9 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
                                                int64_t band_rows, int32_t *serial_state,
                                                int vec_ok, const int32_t *__restrict__ bounds,
                                                int64_t tile_rows, int64_t tile_ntx,
-                                               const uint32_t *big_box, int64_t min_items) {
+                                               const uint32_t *big_box, int64_t min_items,
+                                               mshost::ScratchHeader *hdr,
+                                               unsigned long long *bnd) {
     constexpr int LDSW = BLK_WORDS / 4;  // words per wave in the narrow pass
     static_assert(NGMAX * CPL * 64 <= LDSW, "a row chunk holds at least 64 rows");
     __shared__ uint64_t lx[BLK_WORDS];
@@ -529,7 +777,8 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
         // the blocks holding one take no one-wave item, which the other blocks share.
         const int64_t dealt = wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state,
                                         vec_ok, true, bounds, tile_rows, tile_ntx,
-                                        BlockLds{lx, lc, lslot}, big_box);
+                                        BlockLds{lx, lc, lslot}, big_box, hdr, bnd);
+        if (dealt < 0) return;  // the strip sweep stored every cell
         const int64_t busy = dealt < nblk ? dealt : 0;  // blocks 0 .. busy-1 held a chain
         if ((int64_t)blockIdx.x < busy) return;
         __syncthreads();  // the narrow pass takes the block's LDS as four per-wave regions
@@ -542,7 +791,7 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
                                 nblk * 4);
     } else {
         wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state, vec_ok, false, bounds,
-                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot}, nullptr);
+                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot}, nullptr, hdr, bnd);
     }
 }
 
@@ -562,6 +811,12 @@ __global__ void k_clear_header(mshost::ScratchHeader *hdr) {
 
 // Zero `words` 32-bit words (a context header) on the caller's stream: ordered before the
 // launches that follow it there, which a memset on the null stream is not.
+__global__ void k_zero_u64(uint64_t *p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
 __global__ void k_zero_words(uint32_t *p, int words) {
     for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0u;
 }
@@ -1167,7 +1422,7 @@ template <class TS>
 static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits, int64_t m,
                                       int64_t n, int64_t ldw, ScratchHeader *hdr,
                                       int32_t *serial_state, uint8_t *sat, int32_t *bounds,
-                                      uint32_t *box_rec, ms_square *out) {
+                                      uint32_t *box_rec, ms_square *out, uint64_t *bnd) {
     const int64_t ntx = cdiv(cdiv(n, 64), TS::OWN_WORDS);
     const int64_t ntiles = cdiv(m, TS::TR) * ntx;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 4),
@@ -1183,7 +1438,7 @@ static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits
     hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks),
                        dim3(64 * msk::RESOLVE_WAVES), 0, env.stream,
                        bits, m, n, ldw, ntiles, ntx, hdr, sat, bounds, box_rec, blocks,
-                       serial_state, out);
+                       serial_state, out, reinterpret_cast<unsigned long long *>(bnd));
     return hipGetLastError();
 }
 
@@ -1197,27 +1452,30 @@ int64_t max_probe_tiles(int64_t m, int64_t n) {
 
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out) {
+                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out,
+                             uint64_t *bnd) {
     switch (variant) {
     case 0:
         return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                         box_rec, out);
+                                         box_rec, out, bnd);
     case 1:
         return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                         box_rec, out);
+                                         box_rec, out, bnd);
     case 2:
         return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                        box_rec, out);
+                                        box_rec, out, bnd);
     default:
         return launch_max_square_t<TS3>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                        box_rec, out);
+                                        box_rec, out, bnd);
     }
 }
 
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
                              int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state,
-                             const MapRegions *regions) {
+                             const MapRegions *regions, ScratchHeader *hdr, uint64_t *bnd) {
+    if (!hdr) bnd = nullptr;
+    unsigned long long *bw = reinterpret_cast<unsigned long long *>(bnd);
     const int vec_ok = ((uintptr_t)dp % 16 == 0) && (ld_dp % 4 == 0);
     const int64_t items_bound = cdiv(m, 16) * cdiv(n, 64);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(items_bound, 4),
@@ -1233,12 +1491,26 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
-                           box, min_items);
+                           box, min_items, hdr, bw);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
-                           box, min_items);
+                           box, min_items, hdr, bw);
     }
+    return hipGetLastError();
+}
+
+int64_t strip_words_needed(int64_t m, int64_t n) {
+    if (std::min(m, n) <= STRIP_MIN_SIDE) return 0;
+    return cdiv(cdiv(n, 64), (int64_t)STRIP_WORDS) * m * 2;
+}
+
+hipError_t launch_zero_u64(const LaunchEnv &env, uint64_t *p, int64_t count) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 256 * 8),
+                                                                   (int64_t)env.num_cus * 8));
+    hipLaunchKernelGGL(msk::k_zero_u64, dim3((unsigned)blocks), dim3(256), 0, env.stream, p,
+                       count);
     return hipGetLastError();
 }
 

@@ -24,7 +24,15 @@ struct ScratchHeader {
     // probe block stores the box of its tiles (BOX_RECORD_WORDS words), and the wave that
     // writes the result folds those records into big_box for the map.
     uint32_t big_box[4];
-    uint64_t pad1[8];
+    // Strip sweep (squares too wide for the windowed passes; see strip_words_needed)
+    unsigned long long skey;    // the sweep's best (side, position) key
+    unsigned long long tick;    // strip tickets: epoch << 32 | tickets taken in that launch
+    uint32_t epoch;             // bumped once per search and per sweeping map: tags the strip words
+    uint32_t fin;               // search: the last arrival and the last strip, each counted once
+    uint32_t sdone;             // search: strips finished
+    uint32_t timeout;           // epoch + 1 of a launch whose strip wait gave up (a search
+                                // then reports failure)
+    uint64_t pad1[4];
 };
 static_assert(sizeof(ScratchHeader) == 128, "header layout");
 
@@ -57,9 +65,19 @@ int64_t max_probe_blocks(int num_cus);
 // per tile and `box_rec` the per-block box records, both filled for a map in the same call.
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out);
+                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out,
+                             uint64_t *bnd = nullptr);
 int64_t max_probe_tiles(int64_t m, int64_t n);
 
+// Strip sweep: the recurrence over the whole matrix by many waves, for a square too wide for
+// the windowed passes (map: S above 1984; search: a saturated tile's window beyond one word per
+// lane).  Strips of STRIP_WORDS words; per (strip, row) two 64-bit boundary words, zeroed when
+// allocated (the header's epoch tags them, so the header and the words are zeroed together).
+// Needed only when min(m, n) > STRIP_MIN_SIDE; bnd == nullptr keeps the one-wave sweep.
+constexpr int STRIP_WORDS = 2;
+constexpr int64_t STRIP_MIN_SIDE = 1024;
+int64_t strip_words_needed(int64_t m, int64_t n);
+hipError_t launch_zero_u64(const LaunchEnv &env, uint64_t *p, int64_t count);
 // The map's narrow pass shortens its row bands (and narrows its window) until it has at least
 // this many items per SIMD (4 SIMDs per CU), or reaches its shortest band.
 constexpr int MAP_ITEMS_PER_SIMD = 2;
@@ -77,7 +95,8 @@ struct MapRegions {
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
                              int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state,
-                             const MapRegions *regions = nullptr);
+                             const MapRegions *regions = nullptr, ScratchHeader *hdr = nullptr,
+                             uint64_t *bnd = nullptr);
 
 // Write a constant result (empty matrices).
 // Zero a context header of `bytes` (a multiple of 4, at most 256) on env.stream.
