@@ -445,6 +445,68 @@ def hbm_achievable(dev, reps=5):
     return out
 
 
+WIDE_SHAPES = ((8192, 8192), (4096, 32768), (3000, 40000))
+
+
+def wide_section(L, h, dev, reps):
+    """All-ones matrices whose largest square (min(m, n)) is too wide for the windowed passes, so
+    that the search and the map finish by the strip sweep: ms_max_square alone and ms_square_map
+    (search + map), each the median of `reps` calls timed with HIP events (warm caches).  The
+    side, its corner and the map's maximum are checked against the closed form of an all-ones
+    matrix (side min(m, n), first corner at (side - 1, side - 1))."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    out = {}
+    for (m, n) in WIDE_SHAPES:
+        ldw = (n + 63) // 64
+        a = torch.ones((m, n), dtype=torch.uint8, device=dev)
+        d = torch.empty((m, ldw), dtype=torch.int64, device=dev)
+        if L.ms_pack_u8(h, a.data_ptr(), m, n, n, d.data_ptr(), ldw, sp):
+            raise RuntimeError("ms_pack_u8 failed")
+        del a
+        dp = torch.empty((m, n), dtype=torch.int32, device=dev)
+        res = torch.zeros(3, dtype=torch.int64, device=dev)
+
+        def search():
+            if L.ms_max_square(h, d.data_ptr(), m, n, ldw, res.data_ptr(), sp):
+                raise RuntimeError("ms_max_square failed")
+
+        def both():
+            if L.ms_square_map(h, d.data_ptr(), m, n, ldw, dp.data_ptr(), n, res.data_ptr(), sp):
+                raise RuntimeError("ms_square_map failed")
+
+        side = min(m, n)
+        times = {}
+        for name, fn in (("search", search), ("search_map", both)):
+            fn()
+            torch.cuda.synchronize()
+            if tuple(res.cpu().tolist()) != (side, side - 1, side - 1):
+                raise SystemExit("wide %dx%d: %s result %s, expected side %d at (%d, %d)"
+                                 % (m, n, name, res.cpu().tolist(), side, side - 1, side - 1))
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            times[name] = float(np.median(ts))
+        if int(dp.max().item()) != side:
+            raise SystemExit("wide %dx%d: map maximum differs from the side" % (m, n))
+        key = "ones_%dx%d" % (m, n)
+        out[key] = {"m": m, "n": n, "side": side, "max_square_ms": times["search"],
+                    "square_map_ms": times["search_map"],
+                    "square_map_gcells_s": m * n / (times["search_map"] * 1e-3) / 1e9}
+        log("wide %s: search %.3f ms, search + map %.3f ms" % (key, times["search"],
+                                                               times["search_map"]))
+        del d, dp
+    return out
+
+
 def c4_section(L, h, dev, reps):
     """The 10000-matrix batched workload: ms_max_square_batched in one launch sequence against
     the plain loop of ms_max_square calls, both checked against the oracle's stored results."""
@@ -633,6 +695,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-rect", action="store_true")
     ap.add_argument("--no-cube", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--c4-reps", type=int, default=10)
     ap.add_argument("--hw-queues", type=int, default=8,
                     help="GPU_MAX_HW_QUEUES for this process (0: keep the environment's)")
@@ -899,6 +962,8 @@ def main():
     if not args.no_large:
         extra["large"] = large_section(L, h, dev, [x for x in args.large.split(",") if x],
                                        args.large_reps, golden_all)
+    if not args.no_wide:
+        extra["wide"] = wide_section(L, h, dev, 5)
     if not args.no_c4:
         extra["c4_batched"] = c4_section(L, h, dev, args.c4_reps)
     if not args.no_serve:

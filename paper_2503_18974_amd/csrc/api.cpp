@@ -71,7 +71,8 @@ struct ms_ctx {
     void *scratch = nullptr;
     int64_t state_words = 0;
     int64_t sat_bytes = 0;
-    int64_t strip_words = 0;  // boundary words of the strip sweep (zeroed with the header)
+    void *strips = nullptr;   // boundary words of the strip sweep (zeroed with the header)
+    int64_t strip_words = 0;
     bool dirty = false;
     bool has_forced = false;
     ms_config forced{};
@@ -213,37 +214,65 @@ bool config_valid(const ms_config &cfg) {
 
 // Make sure the context scratch holds the serial-pass state and the probe's saturation bytes
 // for an m x n matrix.
-uint64_t *strips_of(ms_ctx *c);
+// The strip sweep's boundary words, in an allocation of their own (grown apart from the
+// scratch).  They are tagged with the header's epoch, so whenever the header is zeroed they are
+// zeroed too (on the caller's stream, behind the header).
+mshost::ScratchHeader *hdr_of(ms_ctx *c);
 
+ms_status ensure_strips(ms_ctx *c, int64_t need, bool header_zeroed, hipStream_t stream) {
+    const mshost::LaunchEnv env{c->num_cus, stream};
+    if (need > c->strip_words) {
+        if (c->strips) {
+            if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
+            (void)hipFree(c->strips);
+            c->strips = nullptr;
+            c->strip_words = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)need * sizeof(uint64_t)) != hipSuccess) {
+            (void)hipGetLastError();  // without the words the kernels keep the one-wave sweep
+            return mshost::launch_set_strips(env, hdr_of(c), nullptr, 0, 0) == hipSuccess
+                       ? MS_OK
+                       : MS_ERR_HIP;
+        }
+        c->strips = p;
+        c->strip_words = need;
+        header_zeroed = true;  // fresh memory: clear it
+    }
+    if (!header_zeroed) return MS_OK;
+    uint64_t *w = static_cast<uint64_t *>(c->strips);
+    if ((w && mshost::launch_zero_u64(env, w, c->strip_words) != hipSuccess) ||
+        mshost::launch_set_strips(env, hdr_of(c), w, c->strip_words,
+                                  mshost::strip_rows_setting()) != hipSuccess)
+        return MS_ERR_HIP;
+    return MS_OK;
+}
+
+// Make sure the context scratch holds the serial-pass state and the probe's saturation bytes
+// for an m x n matrix, and the strip words that shape may need.
 ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     const int64_t nwords = std::max<int64_t>(1, cdiv(n, 64));
     const int64_t tiles = mshost::max_probe_tiles(m, n);
     const int64_t strips = mshost::strip_words_needed(m, n);
     const mshost::LaunchEnv env{c->num_cus, stream};
-    if (c->scratch && c->state_words >= nwords && c->sat_bytes >= tiles &&
-        c->strip_words >= strips) {
-        if (c->dirty) {
-            // the header's epoch tags the strip words: both start again from zero
+    if (c->scratch && c->state_words >= nwords && c->sat_bytes >= tiles) {
+        const bool zero = c->dirty;
+        if (zero) {
             if (mshost::launch_zero_header(env, c->scratch, sizeof(mshost::ScratchHeader)) !=
-                    hipSuccess ||
-                mshost::launch_zero_u64(env, strips_of(c), c->strip_words) != hipSuccess)
+                hipSuccess)
                 return MS_ERR_HIP;
             c->dirty = false;
         }
-        return MS_OK;
+        return ensure_strips(c, strips, zero, stream);
     }
     const int64_t words = std::max<int64_t>(nwords, c->state_words);
     const int64_t sat = std::max<int64_t>(tiles, c->sat_bytes);
-    const int64_t swords = std::max<int64_t>(strips, c->strip_words);
-    // header | serial state | saturation bytes | per-tile bounds (int32) | probe box records |
-    // strip words
+    // header | serial state | saturation bytes | per-tile bounds (int32) | probe box records
     const size_t bytes = sizeof(mshost::ScratchHeader) + (size_t)words * 64 * 2 * sizeof(int32_t) +
                          (((size_t)sat + 255) & ~(size_t)255) +
                          (((size_t)sat * sizeof(int32_t) + 255) & ~(size_t)255) +
-                         (((size_t)mshost::max_probe_blocks(c->num_cus) *
-                               mshost::BOX_RECORD_WORDS * sizeof(uint32_t) + 255) &
-                          ~(size_t)255) +
-                         (size_t)swords * sizeof(uint64_t);
+                         (size_t)mshost::max_probe_blocks(c->num_cus) *
+                             mshost::BOX_RECORD_WORDS * sizeof(uint32_t);
     if (c->scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return MS_ERR_HIP;
         (void)hipFree(c->scratch);
@@ -256,19 +285,15 @@ ms_status ensure_scratch(ms_ctx *c, int64_t m, int64_t n, hipStream_t stream) {
     // the header is zeroed on the caller's stream, ahead of the search launched there next (a
     // memset on the null stream may still be pending when a non-blocking stream runs the probe,
     // and would then erase keys it pushed)
-    c->scratch = p;
-    c->state_words = words;
-    c->sat_bytes = sat;
-    c->strip_words = swords;
-    if (mshost::launch_zero_header(env, p, sizeof(mshost::ScratchHeader)) != hipSuccess ||
-        mshost::launch_zero_u64(env, strips_of(c), swords) != hipSuccess) {
-        c->scratch = nullptr;
-        c->state_words = c->sat_bytes = c->strip_words = 0;
+    if (mshost::launch_zero_header(env, p, sizeof(mshost::ScratchHeader)) != hipSuccess) {
         (void)hipFree(p);
         return MS_ERR_HIP;
     }
+    c->scratch = p;
+    c->state_words = words;
+    c->sat_bytes = sat;
     c->dirty = false;
-    return MS_OK;
+    return ensure_strips(c, strips, true, stream);
 }
 
 mshost::ScratchHeader *hdr_of(ms_ctx *c) { return static_cast<mshost::ScratchHeader *>(c->scratch); }
@@ -284,19 +309,12 @@ uint32_t *box_records_of(ms_ctx *c) {
         reinterpret_cast<char *>(bounds_of(c)) +
         (((size_t)c->sat_bytes * sizeof(int32_t) + 255) & ~(size_t)255));
 }
-uint64_t *strips_of(ms_ctx *c) {
-    if (c->strip_words == 0) return nullptr;
-    return reinterpret_cast<uint64_t *>(
-        reinterpret_cast<char *>(box_records_of(c)) +
-        (((size_t)mshost::max_probe_blocks(c->num_cus) * mshost::BOX_RECORD_WORDS *
-              sizeof(uint32_t) + 255) & ~(size_t)255));
-}
 // The strip words for an m x n call, or nullptr (the kernels then keep the one-wave sweep)
 // when the scratch holds too few of them for that shape.
 uint64_t *strips_for(ms_ctx *c, int64_t m, int64_t n) {
     const int64_t need = cdiv(cdiv(std::max<int64_t>(n, 1), 64), (int64_t)mshost::STRIP_WORDS) *
                          std::max<int64_t>(m, 1) * 2;
-    return c->strip_words >= need ? strips_of(c) : nullptr;
+    return c->strip_words >= need ? static_cast<uint64_t *>(c->strips) : nullptr;
 }
 int32_t *state_of(ms_ctx *c) {
     return reinterpret_cast<int32_t *>(static_cast<char *>(c->scratch) +
@@ -328,7 +346,7 @@ ms_status run_max_square(ms_ctx *c, const ms_config &cfg, const uint64_t *bits, 
     } else {
         e = mshost::launch_max_square(env, cfg.probe_variant, bits, m, n, ldw, hdr_of(c),
                                       state_of(c), sat_of(c), bounds_of(c), box_records_of(c),
-                                      out, strips_for(c, m, n));
+                                      out);
     }
     if (e != hipSuccess) {
         c->dirty = true;
@@ -392,6 +410,7 @@ ms_status ms_destroy(ms_ctx *ctx) {
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->strips) (void)hipFree(ctx->strips);
     if (ctx->rect_scratch) (void)hipFree(ctx->rect_scratch);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
@@ -470,7 +489,8 @@ ms_status ms_square_map(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t 
                                      hdr_of(c)->big_box};
     hipError_t e = mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m, n,
                                              ld_words, d_dp, ld_dp, &hdr_of(c)->result,
-                                             state_of(c), &regions, hdr_of(c), strips_for(c, m, n));
+                                             state_of(c), &regions, hdr_of(c), strips_for(c, m, n),
+                                             mshost::strip_rows_setting());
     return hip_status(e);
 }
 
@@ -506,7 +526,8 @@ ms_status ms_square_map_from_max(ms_ctx *ctx, const uint64_t *d_bits, int64_t m,
     return hip_status(mshost::launch_square_map(env, cfg.map_cols, cfg.map_band_rows, d_bits, m,
                                                 n, ld_words, d_dp, ld_dp, d_max, state_of(c),
                                                 same ? &regions : nullptr, hdr_of(c),
-                                                strips_for(c, m, n)));
+                                                strips_for(c, m, n),
+                                                mshost::strip_rows_setting()));
 }
 
 ms_status ms_batched_workspace_size(ms_ctx *ctx, const ms_matrix *h_mats, int64_t count,
@@ -871,7 +892,8 @@ ms_status ms_autotune(ms_ctx *ctx, const uint64_t *d_bits, int64_t m, int64_t n,
                                                             ld_dp, &hdr_of(c)->result,
                                                             state_of(c), nullptr,
                                                             hdr_of(c),
-                                                            strips_for(c, m, n)));
+                                                            strips_for(c, m, n),
+                                                            mshost::strip_rows_setting()));
             }, &t);
             if (s == MS_OK && t < best_map) {
                 best_map = t;

@@ -16,6 +16,7 @@
 // k_probe_batched (every tile of every matrix in one grid-stride pass), k_batch_finish (the
 // saturated tiles of every matrix if any, then key -> result per matrix).
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 
 #include "device.hpp"
@@ -213,6 +214,18 @@ __device__ __forceinline__ int64_t strip_takers(int64_t nstrips, int64_t nwave) 
     return nstrips < nwave ? nstrips : nwave;
 }
 
+// Rows a strip hands on at a time (one per lane).  A sweep takes about m / R + nstrips batch
+// times of R t + L (t per row, L the hand-over latency), least at R = sqrt(m L / (nstrips t));
+// measured L / t is about 8 (all-ones 8192^2: R = 32 best, 4096 x 32768: 8-16, 3000 x 40000: 8),
+// so R is the power of two in 8..64 nearest that.  `forced` in 1..64 overrides the choice.
+__device__ __forceinline__ int strip_rows(int64_t m, int64_t nstrips, int forced) {
+    if (forced >= 1 && forced <= WAVE) return forced;
+    const int64_t x = 8 * m / (nstrips > 0 ? nstrips : 1);
+    int r = 8;
+    while (r < WAVE && 2 * (int64_t)r * r <= x) r *= 2;
+    return r;
+}
+
 __device__ __forceinline__ int64_t strip_count(int64_t n) {
     return (((n + 63) >> 6) + mshost::STRIP_WORDS - 1) / mshost::STRIP_WORDS;
 }
@@ -221,7 +234,7 @@ template <bool STORE>
 __device__ void strip_sweep(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                             int32_t *__restrict__ dp, int64_t ld_dp, int64_t s,
                             unsigned long long *bnd, uint32_t epoch, uint32_t *timeout,
-                            Track &tr) {
+                            int R, Track &tr) {
     constexpr int SW = mshost::STRIP_WORDS;
     const int lane = __lane_id();
     const int64_t nwords = (n + 63) >> 6;
@@ -235,23 +248,25 @@ __device__ void strip_sweep(const uint64_t *__restrict__ bits, int64_t m, int64_
 #pragma unroll
     for (int u = 0; u < SW; ++u) H[u] = D[u] = 0;
     int32_t dl = 0;  // dp of the previous row at the column just left of the strip
-    // the strip's words of rows i0 .. i0 + 63, row i0 + l in lane l
+    // the strip's words of rows i0 .. i0 + R - 1, row i0 + l in lane l
     auto load_rows = [&](int64_t i0, uint64_t(&v)[SW]) {
         const int64_t i = i0 + lane;
 #pragma unroll
         for (int u = 0; u < SW; ++u)
-            v[u] = i < m ? row_word(bits + i * ldw, w0 + u, nwords, lastmask) : 0ull;
+            v[u] = (lane < R && i < m) ? row_word(bits + i * ldw, w0 + u, nwords, lastmask)
+                                       : 0ull;
     };
     uint64_t x[SW];
     load_rows(0, x);
-    for (int64_t i0 = 0; i0 < m; i0 += WAVE) {
+    for (int64_t i0 = 0; i0 < m; i0 += R) {
         uint64_t nx[SW];
-        load_rows(i0 + WAVE, nx);
+        load_rows(i0 + R, nx);
         int32_t win = 0, din = 0;
         if (left) {
             const int64_t i = i0 + lane;
             unsigned long long a = tag << 20, b = tag << 20;
-            if (i < m) {
+            const bool mine_row = lane < R && i < m;
+            if (mine_row) {
                 a = load_relaxed(left + 2 * i);
                 b = load_relaxed(left + 2 * i + 1);
             }
@@ -273,7 +288,7 @@ __device__ void strip_sweep(const uint64_t *__restrict__ bits, int64_t m, int64_
             win = (int32_t)(a & 0xFFFFFull);
             din = (int32_t)(b & 0xFFFFFull);
         }
-        const int rows = (int)(m - i0 < WAVE ? m - i0 : WAVE);
+        const int rows = (int)(m - i0 < R ? m - i0 : R);
         int32_t ow = 0, od = 0;
         for (int r = 0; r < rows; ++r) {
             int32_t wc = __builtin_amdgcn_readlane(win, r);  // row run entering the strip
@@ -308,7 +323,7 @@ __device__ void strip_sweep(const uint64_t *__restrict__ bits, int64_t m, int64_
             ow = lane == r ? wc : ow;
             od = lane == r ? dlast : od;
         }
-        if (publish && i0 + lane < m) {
+        if (publish && lane < R && i0 + lane < m) {
             const int64_t i = i0 + lane;
             store_relaxed_u64(mine + 2 * i, (tag << 20) | (unsigned long long)(uint32_t)ow);
             store_relaxed_u64(mine + 2 * i + 1, (tag << 20) | (unsigned long long)(uint32_t)od);
@@ -323,21 +338,22 @@ __device__ void strip_sweep(const uint64_t *__restrict__ bits, int64_t m, int64_
 // epoch for the next launch (every taker read it before its first ticket).
 __device__ void strip_map(const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
                           int32_t *__restrict__ dp, int64_t ld_dp, mshost::ScratchHeader *hdr,
-                          unsigned long long *bnd) {
+                          unsigned long long *bnd, int forced_rows) {
     const int64_t nstrips = strip_count(n);
     const int64_t takers = strip_takers(nstrips, ((int64_t)gridDim.x * blockDim.x) / WAVE);
     if (wave_index() >= takers) return;
-    const uint32_t epoch = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->epoch));
+    const uint32_t epoch = (uint32_t)uniform((int32_t)(load_relaxed(&hdr->done_epoch) >> 32));
+    const int R = strip_rows(m, nstrips, forced_rows);
     for (;;) {
         const int64_t s = take_strip(&hdr->tick, epoch);
         if (s >= nstrips) {
             if (s == nstrips + takers - 1 && __lane_id() == 0)
-                __hip_atomic_store(&hdr->epoch, epoch + 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&hdr->done_epoch, (unsigned long long)(epoch + 1u) << 32,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
         Track tr{0, INT64_MAX};
-        strip_sweep<true>(bits, m, n, ldw, dp, ld_dp, s, bnd, epoch, &hdr->timeout, tr);
+        strip_sweep<true>(bits, m, n, ldw, dp, ld_dp, s, bnd, epoch, &hdr->timeout, R, tr);
     }
 }
 
@@ -392,17 +408,18 @@ __device__ void finalize_wave(const uint64_t *__restrict__ bits, int64_t m, int6
         key = w.v > 0 ? make_key(w.v, w.pos) : 0ull;
     }
     if (lane == 0) {
-        write_result(key, n, &hdr->result);
-        if (failed) hdr->result = ms_square{-1, -1, -1};
-        if (out) *out = hdr->result;
+        ms_square r;
+        write_result(key, n, &r);
+        if (failed) r = ms_square{-1, -1, -1};
+        hdr->result = r;
+        if (out) *out = r;
         hdr->key = 0;
         hdr->serial_flag = 0;
         hdr->nsat = 0;
-        hdr->done = 0;
+        hdr->done_epoch = (unsigned long long)(epoch + 1u) << 32;  // count 0, next epoch
         hdr->skey = 0;
         hdr->fin = 0;
         hdr->sdone = 0;
-        hdr->epoch = epoch + 1u;
     }
 }
 
@@ -431,25 +448,60 @@ __device__ bool fin_arrive(mshost::ScratchHeader *hdr) {
 // 16384^2 blob image (2804 of 3042 tiles saturated) the search takes 440 us one tile per wave
 // and 339 / 343 / 355 us with groups of 2 / 3 / 4.
 constexpr int RESOLVE_GROUP = 2;
+// At most this many waves of a search sweep strips (each takes strip after strip).
+constexpr int64_t RESOLVE_SWEEPERS = 256;
+
+// The strip words the host recorded in the header, if they cover an m x n sweep.
+__device__ __forceinline__ unsigned long long *header_strips(mshost::ScratchHeader *hdr,
+                                                             int64_t m, int64_t n) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(hdr->strips_ptr);
+    return (w && strip_count(n) * m * 2 <= hdr->strip_cap) ? w : nullptr;
+}
+
+// The search's strip sweep, by one of the waves that saw the serial flag (the last wave to
+// arrive among them): strips until none is left, each strip's best pushed into hdr->skey.
+// Returns whether the calling wave writes the result.  Kept out of line: the resolve pass's own
+// code and registers stay as they are without it.
+__device__ __attribute__((noinline)) bool resolve_sweep(
+    const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw,
+    mshost::ScratchHeader *hdr, unsigned long long *bnd, uint32_t epoch, bool last,
+    int forced_rows) {
+    const int lane = __lane_id();
+    const int64_t nstrips = strip_count(n);
+    bool finish = last && fin_arrive(hdr);
+    const int R = strip_rows(m, nstrips, forced_rows);
+    for (;;) {
+        const int64_t st = take_strip(&hdr->tick, epoch);
+        if (st >= nstrips) break;
+        Track tr{0, INT64_MAX};
+        strip_sweep<false>(bits, m, n, ldw, nullptr, 0, st, bnd, epoch, &hdr->timeout, R, tr);
+        const Track w = wave_track(tr);
+        if (lane == 0 && w.v > 0) atomicMax(&hdr->skey, make_key(w.v, w.pos));
+        __threadfence();
+        uint32_t k = 0;
+        if (lane == 0) k = atomicAdd(&hdr->sdone, 1u);
+        k = (uint32_t)__builtin_amdgcn_readfirstlane(k);
+        if (k == (uint32_t)(nstrips - 1) && fin_arrive(hdr)) finish = true;
+    }
+    return finish;
+}
 
 template <class TS>
 __global__ __launch_bounds__(64 * RESOLVE_WAVES) void k_resolve(
     const uint64_t *__restrict__ bits, int64_t m, int64_t n, int64_t ldw, int64_t ntiles,
     int64_t ntx, mshost::ScratchHeader *hdr, const uint8_t *__restrict__ sat,
     int32_t *__restrict__ bounds, const uint32_t *__restrict__ box_rec, int64_t nrec,
-    int32_t *serial_state, ms_square *out, unsigned long long *bnd) {
+    int32_t *serial_state, ms_square *out) {
     __shared__ ResolveLds L;
     const int lane = __lane_id();
     const int64_t wave = wave_index();
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int64_t nblk = gridDim.x;
     const uint32_t nsat = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->nsat));
-    // read before this wave's completion count, so before the result's wave bumps it
-    const uint32_t epoch = (uint32_t)uniform((int32_t)load_relaxed_u32(&hdr->epoch));
-    const bool strips = bnd != nullptr;
     if (nsat == 0) {
         if (wave == 0)
-            finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, strips, epoch);
+            finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, false,
+                          (uint32_t)(load_relaxed(&hdr->done_epoch) >> 32));
         return;
     }
     if ((int64_t)nsat <= nblk) {
@@ -494,39 +546,31 @@ __global__ __launch_bounds__(64 * RESOLVE_WAVES) void k_resolve(
         }
     }
     __threadfence();
-    uint32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(&hdr->done, 1u);
-    prev = (uint32_t)__shfl((int32_t)prev, 0);
+    unsigned long long prev64 = 0;
+    if (lane == 0) prev64 = atomicAdd(&hdr->done_epoch, 1ull);
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)prev64);
+    const uint32_t epoch = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(prev64 >> 32));
     const bool last = prev == (uint32_t)(nwave - 1);
     if (last) __threadfence();
-    // Every wave that raised the flag did so before its completion count, so the last wave sees
-    // it; an earlier wave that misses it only leaves the sweep to the others.
-    const bool sweep = strips && uniform((int32_t)load_relaxed_u32(&hdr->serial_flag)) != 0;
+    // The possible sweepers: the last few waves to arrive (the last one among them).  Every wave
+    // that raised the flag did so before its completion count, so the last wave sees it; an
+    // earlier one that misses it only leaves the sweep to the others.  The other waves read
+    // nothing more (an extra read per wave here measured 25 % slower searches).
     const int64_t nstrips = strip_count(n);
-    // the sweepers: the last strip_takers waves to arrive (the last one among them), which are
-    // the likeliest to have seen the flag
-    if (!sweep || nwave - 1 - (int64_t)prev >= strip_takers(nstrips, nwave)) {
-        if (last) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, strips,
-                                epoch);
+    const int64_t takers = strip_takers(nstrips, nwave < RESOLVE_SWEEPERS ? nwave
+                                                                           : RESOLVE_SWEEPERS);
+    unsigned long long *bnd = nullptr;
+    if (nwave - 1 - (int64_t)prev < takers &&
+        uniform((int32_t)load_relaxed_u32(&hdr->serial_flag)) != 0)
+        bnd = header_strips(hdr, m, n);
+    if (!bnd) {
+        // with the flag raised and no strip words for this shape: the one-wave serial pass
+        if (last)
+            finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, false, epoch);
         return;
     }
-    // A square too wide for the resolve pass: the result waits for both the last wave's arrival
-    // and the last strip.
-    bool finish = last && fin_arrive(hdr);
-    for (;;) {
-        const int64_t st = take_strip(&hdr->tick, epoch);
-        if (st >= nstrips) break;
-        Track tr{0, INT64_MAX};
-        strip_sweep<false>(bits, m, n, ldw, nullptr, 0, st, bnd, epoch, &hdr->timeout, tr);
-        const Track w = wave_track(tr);
-        if (lane == 0 && w.v > 0) atomicMax(&hdr->skey, make_key(w.v, w.pos));
-        __threadfence();
-        uint32_t k = 0;
-        if (lane == 0) k = atomicAdd(&hdr->sdone, 1u);
-        k = (uint32_t)__builtin_amdgcn_readfirstlane(k);
-        if (k == (uint32_t)(nstrips - 1) && fin_arrive(hdr)) finish = true;
-    }
-    if (finish) finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, strips, epoch);
+    if (resolve_sweep(bits, m, n, ldw, hdr, bnd, epoch, last, hdr->strip_rows_forced))
+        finalize_wave(bits, m, n, ldw, hdr, serial_state, out, box_rec, nrec, true, epoch);
 }
 
 // The narrow pass of the map (one wave per item, windows of NGMAX groups of 64 * CPL columns):
@@ -615,13 +659,13 @@ __device__ int64_t wide_pass(const uint64_t *__restrict__ bits, int64_t m, int64
                           int32_t *serial_state, int vec_ok, bool region,
                           const int32_t *__restrict__ bounds, int64_t tile_rows,
                           int64_t tile_ntx, BlockLds L, const uint32_t *box,
-                          mshost::ScratchHeader *hdr, unsigned long long *bnd) {
+                          mshost::ScratchHeader *hdr, unsigned long long *bnd, int forced_rows) {
     constexpr int64_t GW = 256, NGB = 8, WIN = NGB * GW, REACH = WIN - 64;
     constexpr int64_t TILE_COLS = 64 * mshost::PROBE_TILE_WORDS;
     const int64_t hc = (S + 63) & ~(int64_t)63;
     if (hc > REACH) {
         if (bnd) {  // every wave of the launch sweeps strips; every cell is stored
-            strip_map(bits, m, n, ldw, dp, ld_dp, hdr, bnd);
+            strip_map(bits, m, n, ldw, dp, ld_dp, hdr, bnd, forced_rows);
             return -1;
         }
         if (blockIdx.x == 0 && threadIdx.x < WAVE) {
@@ -761,7 +805,7 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
                                                int64_t tile_rows, int64_t tile_ntx,
                                                const uint32_t *big_box, int64_t min_items,
                                                mshost::ScratchHeader *hdr,
-                                               unsigned long long *bnd) {
+                                               unsigned long long *bnd, int forced_rows) {
     constexpr int LDSW = BLK_WORDS / 4;  // words per wave in the narrow pass
     static_assert(NGMAX * CPL * 64 <= LDSW, "a row chunk holds at least 64 rows");
     __shared__ uint64_t lx[BLK_WORDS];
@@ -777,7 +821,7 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
         // the blocks holding one take no one-wave item, which the other blocks share.
         const int64_t dealt = wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state,
                                         vec_ok, true, bounds, tile_rows, tile_ntx,
-                                        BlockLds{lx, lc, lslot}, big_box, hdr, bnd);
+                                        BlockLds{lx, lc, lslot}, big_box, hdr, bnd, forced_rows);
         if (dealt < 0) return;  // the strip sweep stored every cell
         const int64_t busy = dealt < nblk ? dealt : 0;  // blocks 0 .. busy-1 held a chain
         if ((int64_t)blockIdx.x < busy) return;
@@ -791,7 +835,8 @@ __global__ __launch_bounds__(256, 5) void k_dpmap(const uint64_t *__restrict__ b
                                 nblk * 4);
     } else {
         wide_pass(bits, m, n, ldw, dp, ld_dp, S, band_rows, serial_state, vec_ok, false, bounds,
-                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot}, nullptr, hdr, bnd);
+                  tile_rows, tile_ntx, BlockLds{lx, lc, lslot}, nullptr, hdr, bnd,
+                  forced_rows);
     }
 }
 
@@ -815,6 +860,15 @@ __global__ void k_zero_u64(uint64_t *p, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0ull;
+}
+
+__global__ void k_set_strips(mshost::ScratchHeader *hdr, unsigned long long words, int64_t count,
+                             int forced_rows) {
+    if (threadIdx.x == 0) {
+        hdr->strips_ptr = words;
+        hdr->strip_cap = count;
+        hdr->strip_rows_forced = forced_rows;
+    }
 }
 
 __global__ void k_zero_words(uint32_t *p, int words) {
@@ -1422,7 +1476,7 @@ template <class TS>
 static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits, int64_t m,
                                       int64_t n, int64_t ldw, ScratchHeader *hdr,
                                       int32_t *serial_state, uint8_t *sat, int32_t *bounds,
-                                      uint32_t *box_rec, ms_square *out, uint64_t *bnd) {
+                                      uint32_t *box_rec, ms_square *out) {
     const int64_t ntx = cdiv(cdiv(n, 64), TS::OWN_WORDS);
     const int64_t ntiles = cdiv(m, TS::TR) * ntx;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(ntiles, 4),
@@ -1438,7 +1492,7 @@ static hipError_t launch_max_square_t(const LaunchEnv &env, const uint64_t *bits
     hipLaunchKernelGGL(msk::k_resolve<TS>, dim3((unsigned)rblocks),
                        dim3(64 * msk::RESOLVE_WAVES), 0, env.stream,
                        bits, m, n, ldw, ntiles, ntx, hdr, sat, bounds, box_rec, blocks,
-                       serial_state, out, reinterpret_cast<unsigned long long *>(bnd));
+                       serial_state, out);
     return hipGetLastError();
 }
 
@@ -1452,28 +1506,28 @@ int64_t max_probe_tiles(int64_t m, int64_t n) {
 
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out,
-                             uint64_t *bnd) {
+                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out) {
     switch (variant) {
     case 0:
         return launch_max_square_t<TS0>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                         box_rec, out, bnd);
+                                         box_rec, out);
     case 1:
         return launch_max_square_t<TS1>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                         box_rec, out, bnd);
+                                         box_rec, out);
     case 2:
         return launch_max_square_t<TS2>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                        box_rec, out, bnd);
+                                        box_rec, out);
     default:
         return launch_max_square_t<TS3>(env, bits, m, n, ldw, hdr, serial_state, sat, bounds,
-                                        box_rec, out, bnd);
+                                        box_rec, out);
     }
 }
 
 hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
                              int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state,
-                             const MapRegions *regions, ScratchHeader *hdr, uint64_t *bnd) {
+                             const MapRegions *regions, ScratchHeader *hdr, uint64_t *bnd,
+                             int strip_rows) {
     if (!hdr) bnd = nullptr;
     unsigned long long *bw = reinterpret_cast<unsigned long long *>(bnd);
     const int vec_ok = ((uintptr_t)dp % 16 == 0) && (ld_dp % 4 == 0);
@@ -1491,13 +1545,22 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
     if (map_cols == 8) {
         hipLaunchKernelGGL((msk::k_dpmap<1, 8>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
-                           box, min_items, hdr, bw);
+                           box, min_items, hdr, bw, strip_rows);
     } else {
         hipLaunchKernelGGL((msk::k_dpmap<2, 4>), g, b, 0, env.stream, bits, m, n, ldw, dp, ld_dp,
                            maxsq, (int64_t)band_rows, serial_state, vec_ok, bounds, trows, tntx,
-                           box, min_items, hdr, bw);
+                           box, min_items, hdr, bw, strip_rows);
     }
     return hipGetLastError();
+}
+
+int strip_rows_setting() {
+    static const int v = [] {
+        const char *e = std::getenv("MAXSQ_STRIP_ROWS");
+        const int r = e ? std::atoi(e) : 0;
+        return (r >= 1 && r <= 64) ? r : 0;
+    }();
+    return v;
 }
 
 int64_t strip_words_needed(int64_t m, int64_t n) {
@@ -1511,6 +1574,14 @@ hipError_t launch_zero_u64(const LaunchEnv &env, uint64_t *p, int64_t count) {
                                                                    (int64_t)env.num_cus * 8));
     hipLaunchKernelGGL(msk::k_zero_u64, dim3((unsigned)blocks), dim3(256), 0, env.stream, p,
                        count);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_strips(const LaunchEnv &env, ScratchHeader *hdr, uint64_t *words,
+                             int64_t count, int forced_rows) {
+    hipLaunchKernelGGL(msk::k_set_strips, dim3(1), dim3(64), 0, env.stream, hdr,
+                       reinterpret_cast<unsigned long long>(words), words ? count : 0,
+                       forced_rows);
     return hipGetLastError();
 }
 

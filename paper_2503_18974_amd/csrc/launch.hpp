@@ -16,25 +16,38 @@ struct ScratchHeader {
     uint32_t serial_flag;       // a square was too wide for the resolve pass
     uint32_t nsat;              // saturated tiles found by the probe
     ms_square result;           // last result (read by the map pass)
-    uint32_t done;              // waves of the resolve pass that have finished
-    uint32_t pad0;
+    // epoch << 32 | waves of the resolve pass that have finished.  The epoch counts searches and
+    // sweeping maps and tags the strip words; sharing the word, every wave's completion count
+    // returns it with no read of its own.
+    unsigned long long done_epoch;
     // Bounding box of the probe tiles whose largest side may exceed the narrow map's region
     // halo (bound above REGION_SMALL, or saturated), as {2^30 - first tile row, last tile row
     // + 1, 2^30 - first tile column, last tile column + 1}, all zero when there is none: each
     // probe block stores the box of its tiles (BOX_RECORD_WORDS words), and the wave that
     // writes the result folds those records into big_box for the map.
     uint32_t big_box[4];
-    // Strip sweep (squares too wide for the windowed passes; see strip_words_needed)
+    uint64_t pad1[8];
+    // Second 128-byte line: the strip sweep (squares too wide for the windowed passes; see
+    // strip_words_needed), apart from the words above that every wave of a search hits with
+    // atomics (a per-wave read of the epoch in that line measured 25 % slower searches).
     unsigned long long skey;    // the sweep's best (side, position) key
     unsigned long long tick;    // strip tickets: epoch << 32 | tickets taken in that launch
-    uint32_t epoch;             // bumped once per search and per sweeping map: tags the strip words
+    uint32_t pad4;
     uint32_t fin;               // search: the last arrival and the last strip, each counted once
     uint32_t sdone;             // search: strips finished
     uint32_t timeout;           // epoch + 1 of a launch whose strip wait gave up (a search
                                 // then reports failure)
-    uint64_t pad1[4];
+    // Where the strip words are (0: none) and how many, and a forced batch height (0: the
+    // kernels choose).  Written by the host's set-up kernel whenever the words or the header are
+    // (re)initialised, so the search reads them from here rather than from its arguments.
+    unsigned long long strips_ptr;
+    int64_t strip_cap;
+    int32_t strip_rows_forced;
+    int32_t pad2;
+    uint64_t pad3[9];
 };
-static_assert(sizeof(ScratchHeader) == 128, "header layout");
+static_assert(sizeof(ScratchHeader) == 256, "header layout: two 128-byte lines");
+static_assert(offsetof(ScratchHeader, skey) == 128, "strip fields start the second line");
 
 // Erosion tile variants compiled into the library.
 struct ProbeVariant {
@@ -65,8 +78,7 @@ int64_t max_probe_blocks(int num_cus);
 // per tile and `box_rec` the per-block box records, both filled for a map in the same call.
 hipError_t launch_max_square(const LaunchEnv &env, int variant, const uint64_t *bits, int64_t m,
                              int64_t n, int64_t ldw, ScratchHeader *hdr, int32_t *serial_state,
-                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out,
-                             uint64_t *bnd = nullptr);
+                             uint8_t *sat, int32_t *bounds, uint32_t *box_rec, ms_square *out);
 int64_t max_probe_tiles(int64_t m, int64_t n);
 
 // Strip sweep: the recurrence over the whole matrix by many waves, for a square too wide for
@@ -76,8 +88,13 @@ int64_t max_probe_tiles(int64_t m, int64_t n);
 // Needed only when min(m, n) > STRIP_MIN_SIDE; bnd == nullptr keeps the one-wave sweep.
 constexpr int STRIP_WORDS = 2;
 constexpr int64_t STRIP_MIN_SIDE = 1024;
+// Rows per strip batch: 0 lets the kernels choose; 1..64 forces it (MAXSQ_STRIP_ROWS).
+int strip_rows_setting();
 int64_t strip_words_needed(int64_t m, int64_t n);
 hipError_t launch_zero_u64(const LaunchEnv &env, uint64_t *p, int64_t count);
+// Record the strip words (may be null) and the forced batch height in the header.
+hipError_t launch_set_strips(const LaunchEnv &env, ScratchHeader *hdr, uint64_t *words,
+                             int64_t count, int forced_rows);
 // The map's narrow pass shortens its row bands (and narrows its window) until it has at least
 // this many items per SIMD (4 SIMDs per CU), or reaches its shortest band.
 constexpr int MAP_ITEMS_PER_SIMD = 2;
@@ -96,7 +113,7 @@ hipError_t launch_square_map(const LaunchEnv &env, int map_cols, int band_rows,
                              const uint64_t *bits, int64_t m, int64_t n, int64_t ldw, int32_t *dp,
                              int64_t ld_dp, const ms_square *maxsq, int32_t *serial_state,
                              const MapRegions *regions = nullptr, ScratchHeader *hdr = nullptr,
-                             uint64_t *bnd = nullptr);
+                             uint64_t *bnd = nullptr, int strip_rows = 0);
 
 // Write a constant result (empty matrices).
 // Zero a context header of `bytes` (a multiple of 4, at most 256) on env.stream.
