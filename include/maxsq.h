@@ -21,8 +21,12 @@
  *
  * Ownership and memory: every buffer argument is caller-owned device memory (a result may
  * also be pinned host memory from hipHostMalloc).  The library never frees or keeps a caller
- * pointer after the enqueued work completes.  A context owns only its small device scratch
- * (sized to the largest matrix it has seen) and its tuning table.
+ * pointer after the enqueued work completes.  A context owns only its device scratch (sized
+ * to the largest matrix it has seen) and its tuning table.  For matrices with min(m, n) > 1024
+ * the scratch includes the boundary words of the strip sweep (the pass for squares too wide
+ * for the windowed ones): 16 bytes per 128 columns and row, as much as the packed matrix.  If
+ * they cannot be allocated, such squares are finished by one wave instead (slower, same
+ * result).
  *
  * Streams: every call enqueues its kernels on `stream` (a hipStream_t; NULL = the null
  * stream) and returns without waiting; results are valid once that stream has reached the
